@@ -1,0 +1,152 @@
+#!/usr/bin/env python3
+"""Benchmark: S/T/V/(ab|P) quadrature throughput (pair-points per second) on one MI355X.
+
+One step = one ps_compute of the whole job (grid generation, function and potential evaluation,
+every contraction, reductions, symmetrisation and the (P|Q) Cholesky) with outputs left in HBM.
+The workload is the bent triatomic with the quadruple-zeta-sized basis on three refined
+96x96x48-point grids in FP64 (--workload picks another).  Prints one JSON line.
+
+  roofline      the contraction kernel (the dominant kernel): algorithmic FLOPs per launch
+                (2 per pair-point) over the launch's mean duration, measured with HIP events the
+                library records around it on its own stream, against the MI355X FP64 (or FP32 for
+                the mixed path) dense peak.
+  cpu_baseline  the FP64 CPU oracle timed on a seeded sample of the same job's output elements;
+                the same sample gives the stated max-abs error of the GPU outputs.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6e12, "mixed": 157.3e12}  # MI355X dense FP64 / FP32 matrix peaks, FLOP/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="triatomic_qz",
+                    choices=["triatomic_qz", "triatomic_5z", "diatomic_small", "hydrocarbon9"])
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=600, help="abP elements in the oracle sample")
+    ap.add_argument("--tiling", default="0,0,0", help="wm,wn,ksplit (0 = library default)")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "contract_traffic.json"))
+    return ap.parse_args()
+
+
+def sample_elements(job, n_abp, rng):
+    """Seeded sample of output elements of every kind (S, T, V, PQ, abP)."""
+    nb, na = job.n_bf, job.n_aux
+    kinds, I, J, K = [], [], [], []
+    for kind, n in ((0, 6), (1, 6), (2, 6), (3, 6)):
+        lim = na if kind == 3 else nb
+        for _ in range(n):
+            a, b = sorted(rng.integers(0, lim, size=2))
+            kinds.append(kind); I.append(a); J.append(b); K.append(0)
+    for _ in range(n_abp):
+        a, b = sorted(rng.integers(0, nb, size=2))
+        kinds.append(4); I.append(a); J.append(b); K.append(int(rng.integers(0, na)))
+    return np.array(kinds), np.array(I), np.array(J), np.array(K)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this "
+                                   "build (see the sharding paragraph of the design document)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2510_15204_amd import psint
+    from paper_2510_15204_amd import workloads as W
+
+    job = W.WORKLOADS[args.workload]()
+    prec = args.precision or job.precision
+    ctx = psint.Context(0)
+    wm, wn, ks = (int(x) for x in args.tiling.split(","))
+    if wm or wn or ks:
+        ctx.set_tiling(wm, wn, ks)
+    # device outputs allocated once; the job's inputs are a few KB of host structs
+    dev = torch.device("cuda:0")
+    nb, na = job.n_bf, job.n_aux
+    outs = {"S": torch.empty((nb, nb), dtype=torch.float64, device=dev),
+            "T": torch.empty((nb, nb), dtype=torch.float64, device=dev),
+            "V": torch.empty((nb, nb), dtype=torch.float64, device=dev),
+            "PQ": torch.empty((na, na), dtype=torch.float64, device=dev),
+            "PQ_chol": torch.empty((na, na), dtype=torch.float64, device=dev),
+            "abP": torch.empty((na, nb, nb), dtype=torch.float64, device=dev)}
+    print(f"[bench] workload={job.name} precision={prec} n_bf={nb} n_aux={na}", flush=True)
+    for i in range(args.warmup):
+        ctx.compute(job, precision=prec, device=True, out_tensors=outs)
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", flush=True)
+    torch.cuda.synchronize()
+    lat, contract_ms, stats = [], [], None
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        s0 = time.perf_counter()
+        _, stats, rc = ctx.compute(job, precision=prec, device=True, out_tensors=outs)
+        lat.append((time.perf_counter() - s0) * 1e3)
+        contract_ms.append(stats["contract_ms"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"[bench] {args.steps} steps in {elapsed:.3f}s", flush=True)
+    pp = stats["pair_points"]
+    value = pp * args.steps / elapsed
+    flops = stats["contract_flops"]
+    mean_contract_s = float(np.mean(contract_ms)) / 1e3
+    achieved = flops / mean_contract_s
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            tj = json.load(open(args.traffic_json))
+            if tj.get("workload") == job.name and tj.get("precision") == prec:
+                traffic = tj.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK[prec], "traffic": traffic,
+                "kernel": "contract_mixed" if prec == "mixed" else "contract_f64",
+                "flops_per_launch": flops, "mean_launch_ms": mean_contract_s * 1e3}
+    out = {"metric": "S/T/V/(ab|P) quadrature pair·points/s at stated error vs FP64; p99 job latency",
+           "value": value, "unit": "pair·points/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == "fp64" else "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": job.name, "atoms": job.n_atoms, "n_bf": nb, "n_aux": na,
+                      "grids": int(stats["n_grids"]), "points": int(stats["n_points"]),
+                      "pair_points_per_step": pp, "precision": prec},
+           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+           "roofline": roofline}
+    if not args.no_cpu_baseline:
+        import oracle as O
+        rng = np.random.default_rng(15204)
+        kinds, I, J, K = sample_elements(job, args.cpu_sample, rng)
+        cores = O.set_threads(0)
+        c0 = time.perf_counter()
+        vals, wpp = O.compute_elements(job, kinds, I, J, K)
+        cdt = time.perf_counter() - c0
+        host = {k: v.cpu().numpy() for k, v in outs.items()}
+        got = np.empty(len(kinds))
+        for e, (kd, a, b, p) in enumerate(zip(kinds, I, J, K)):
+            got[e] = host["abP"][p, a, b] if kd == 4 else host[("S", "T", "V", "PQ")[kd]][a, b]
+        err = {name: float(np.max(np.abs(got[kinds == kd] - vals[kinds == kd])))
+               for kd, name in enumerate(("S", "T", "V", "PQ", "abP"))}
+        out["cpu_baseline"] = {"value": wpp / cdt, "unit": "pair·points/s", "cores": int(cores),
+                               "kind": "oracle",
+                               "sample": f"{len(kinds)} seeded elements (6 each of S/T/V/PQ, "
+                                         f"{args.cpu_sample} of (ab|P)) of the same job, "
+                                         f"{wpp:.3e} pair-points in {cdt:.1f} s"}
+        out["error_vs_fp64_oracle"] = err
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

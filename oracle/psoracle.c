@@ -415,7 +415,8 @@ int orc_eval(int32_t what, const double* fn, const double* center, int64_t npts,
 /* Routing of integrals to grids (3-atom subsets; the paper builds polyatomics from them).     */
 /* Readings: N = 2 uses one unrefined grid.  N >= 3 uses G(A,B|C) for every pair and every     */
 /* third atom; the "pair grid" of (X,Y) is G(X,Y|C*) with C* the atom nearest the midpoint;    */
-/* one-centre blocks of X live on the pair grid of X and its nearest neighbour nn(X).          */
+/* one-centre blocks of X live on the pair grid of X and its nearest neighbour nn(X).  "Nearest" */
+/* counts distances equal within 1e-10 bohr as ties, broken by the lower atom index.            */
 /* ------------------------------------------------------------------------------------------ */
 
 static int nearest_atom(const orc_job* J, int X) {
@@ -424,7 +425,7 @@ static int nearest_atom(const orc_job* J, int X) {
   for (int c = 0; c < J->n_atoms; ++c) {
     if (c == X) continue;
     double d = dist3(J->xyz + 3 * X, J->xyz + 3 * c);
-    if (best < 0 || d < bd) { best = c; bd = d; }
+    if (best < 0 || d < bd - 1e-10) { best = c; bd = d; }
   }
   return best;
 }
@@ -437,7 +438,7 @@ static int nearest_to_midpoint(const orc_job* J, int A, int B) {
   for (int c = 0; c < J->n_atoms; ++c) {
     if (c == A || c == B) continue;
     double d = dist3(M, J->xyz + 3 * c);
-    if (best < 0 || d < bd) { best = c; bd = d; }
+    if (best < 0 || d < bd - 1e-10) { best = c; bd = d; }
   }
   return best;
 }

@@ -1,0 +1,531 @@
+// C ABI of the library (include/psint.h): contexts, synchronous jobs, inspection hooks.  The
+// serving entry points (ps_submit / ps_wait) live in serve.cpp.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "jobs.h"
+
+namespace psint {
+
+hipError_t launch_eval(bool fp32, const SegDev* segs, int nseg, int64_t nblocks, const GridDev* grids,
+                       const double* lines, const ShellDev* shells, const MEntry* ments, const WColDev* wcols,
+                       hipStream_t st);
+hipError_t launch_contract_f64(int wm, int wn, const TaskDev* tasks, const TileDev* tiles, int ntiles, double* ws,
+                               hipStream_t st);
+hipError_t launch_contract_mixed(int wm, int wn, const TaskDev* tasks, const TileDev* tiles, int ntiles, double* ws,
+                                 hipStream_t st);
+hipError_t launch_reduce(int wm, int wn, const TaskDev* tasks, const RedDev* reds, const int32_t* items, int nitems,
+                         const double* ws, hipStream_t st);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+hipError_t launch_symmetrize(double* X, int n, hipStream_t st);
+hipError_t launch_cholesky(const double* A, double* L, int n, int* status, hipStream_t st);
+hipError_t launch_grid_points(const GridDev& G, const double* lines, const double* RA, double* xyzw, hipStream_t st);
+hipError_t launch_eval_points(int what, const ShellDev& sh, const MEntry& me, const double* c, const double* X,
+                              const double* Y, const double* Z, int64_t n, double* out, hipStream_t st);
+
+namespace {
+double factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+constexpr double kPi = 3.141592653589793238462643383279502884;
+}  // namespace
+
+#define HIP_TRY(call)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);                          \
+      return PS_E_DEVICE;                                                                    \
+    }                                                                                        \
+  } while (0)
+
+int32_t ensure_pinned(ps_ctx* ctx, Slot& s, size_t bytes) {
+  if (s.pinned_size >= bytes) return PS_OK;
+  if (s.pinned) (void)hipHostFree(s.pinned);
+  s.pinned = nullptr;
+  s.pinned_size = 0;
+  size_t want = bytes + bytes / 4 + 4096;
+  HIP_TRY(hipHostMalloc(&s.pinned, want, hipHostMallocDefault));
+  s.pinned_size = want;
+  return PS_OK;
+}
+
+int32_t ensure_arena(ps_ctx* ctx, Slot& s, size_t bytes) {
+  if (s.arena_size >= bytes) return PS_OK;
+  if (s.arena) {
+    HIP_TRY(hipStreamSynchronize(s.stream));
+    (void)hipFree(s.arena);
+  }
+  s.arena = nullptr;
+  s.arena_size = 0;
+  HIP_TRY(hipMalloc(&s.arena, bytes));
+  s.arena_size = bytes;
+  return PS_OK;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+void compute_layout(const Plan& p, Layout& L) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + bytes, 256);
+    return r;
+  };
+  L.items_host.clear();
+  for (auto& ps : p.passes)
+    for (auto& v : ps.red_by_phase) L.items_host.insert(L.items_host.end(), v.begin(), v.end());
+  L.grids = take(p.grids.size() * sizeof(GridDev));
+  L.lines = take(p.lines.size() * sizeof(double));
+  L.shells = take(p.shells.size() * sizeof(ShellDev));
+  L.ments = take(p.ments.size() * sizeof(MEntry));
+  L.wcols = take(p.wcols.size() * sizeof(WColDev));
+  L.segs = take(p.segs.size() * sizeof(SegDev));
+  L.tasks = take(p.tasks.size() * sizeof(TaskDev));
+  L.tiles = take(p.tiles.size() * sizeof(TileDev));
+  L.reds = take(p.reds.size() * sizeof(RedDev));
+  L.ints = take(p.ints.size() * sizeof(int32_t));
+  L.items = take(L.items_host.size() * sizeof(int32_t));
+  L.status = take(64);
+  L.meta_end = o;
+  L.arrays = take(p.max_array_bytes);
+  L.ws = take(p.max_ws_bytes);
+  L.out = take((size_t)p.out_elems * sizeof(double));
+  L.total = o;
+}
+
+// Fill the pinned staging buffer with the job's tables, pointers bound to the arena at `base`.
+static void stage_meta(const Plan& p, const Layout& L, char* base, char* host) {
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(host + off, src, bytes);
+  };
+  std::vector<GridDev> grids(p.grids.size());
+  for (size_t i = 0; i < p.grids.size(); ++i) grids[i] = p.grids[i].dev;
+  put(L.grids, grids.data(), grids.size() * sizeof(GridDev));
+  put(L.lines, p.lines.data(), p.lines.size() * sizeof(double));
+  put(L.shells, p.shells.data(), p.shells.size() * sizeof(ShellDev));
+  put(L.ments, p.ments.data(), p.ments.size() * sizeof(MEntry));
+  put(L.wcols, p.wcols.data(), p.wcols.size() * sizeof(WColDev));
+  std::vector<SegDev> segs(p.segs.size());
+  for (size_t i = 0; i < p.segs.size(); ++i) {
+    segs[i] = p.segs[i].dev;
+    segs[i].arr0 = base + L.arrays + p.arrays[p.segs[i].arr0].offset;
+    segs[i].arr1 = p.segs[i].arr1 >= 0 ? base + L.arrays + p.arrays[p.segs[i].arr1].offset : nullptr;
+  }
+  put(L.segs, segs.data(), segs.size() * sizeof(SegDev));
+  const int32_t* ints_dev = (const int32_t*)(base + L.ints);
+  double* out_dev = (double*)(base + L.out);
+  std::vector<TaskDev> tasks(p.tasks.size());
+  for (size_t i = 0; i < p.tasks.size(); ++i) {
+    const TaskHost& th = p.tasks[i];
+    TaskDev d = th.dev;
+    d.U = base + L.arrays + p.arrays[th.U].offset;
+    d.V = base + L.arrays + p.arrays[th.V].offset;
+    d.Y = base + L.arrays + p.arrays[th.Y].offset;
+    d.nfU = p.arrays[th.U].nf;
+    d.nfV = p.arrays[th.V].nf;
+    d.nfY = p.arrays[th.Y].nf;
+    d.nchunks = p.grids[th.grid].dev.npad / KC;
+    d.pairs = ints_dev + th.pairs_off;
+    d.mapU = ints_dev + reinterpret_cast<intptr_t>(th.dev.mapU);
+    d.mapV = ints_dev + reinterpret_cast<intptr_t>(th.dev.mapV);
+    d.mapY = ints_dev + reinterpret_cast<intptr_t>(th.dev.mapY);
+    d.out = out_dev + th.out_off;
+    d.outm = th.outm_off >= 0 ? out_dev + th.outm_off : nullptr;
+    tasks[i] = d;
+  }
+  put(L.tasks, tasks.data(), tasks.size() * sizeof(TaskDev));
+  put(L.tiles, p.tiles.data(), p.tiles.size() * sizeof(TileDev));
+  put(L.reds, p.reds.data(), p.reds.size() * sizeof(RedDev));
+  put(L.ints, p.ints.data(), p.ints.size() * sizeof(int32_t));
+  put(L.items, L.items_host.data(), L.items_host.size() * sizeof(int32_t));
+  std::memset(host + L.status, 0, 64);
+}
+
+// Enqueue every step of a planned job on slot s (no synchronisation).  Events bracket the device
+// work and the contraction launches.
+int32_t enqueue_job(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L) {
+  char* base = (char*)s.arena;
+  hipStream_t st = s.stream;
+  HIP_TRY(hipEventRecord(s.ev_start, st));
+  HIP_TRY(hipMemcpyAsync(base, s.pinned, L.meta_end, hipMemcpyHostToDevice, st));
+  double* out = (double*)(base + L.out);
+  HIP_TRY(launch_fill(out, p.out_elems, 0.0, st));
+  const GridDev* grids = (const GridDev*)(base + L.grids);
+  const double* lines = (const double*)(base + L.lines);
+  const SegDev* segs = (const SegDev*)(base + L.segs);
+  const TaskDev* tasks = (const TaskDev*)(base + L.tasks);
+  const TileDev* tiles = (const TileDev*)(base + L.tiles);
+  const RedDev* reds = (const RedDev*)(base + L.reds);
+  const int32_t* items = (const int32_t*)(base + L.items);
+  double* ws = (double*)(base + L.ws);
+  const bool mixed = p.precision == PS_PREC_MIXED;
+  size_t item_pos = 0;
+  s.n_contract = 0;
+  for (size_t pi = 0; pi < p.passes.size(); ++pi) {
+    const Pass& ps = p.passes[pi];
+    HIP_TRY(launch_eval(mixed, segs + ps.seg0, ps.seg1 - ps.seg0, ps.eval_blocks, grids, lines,
+                        (const ShellDev*)(base + L.shells), (const MEntry*)(base + L.ments),
+                        (const WColDev*)(base + L.wcols), st));
+    if ((int)s.ev_contract.size() < 2 * (int)(pi + 1)) {
+      hipEvent_t e0, e1;
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      s.ev_contract.push_back(e0);
+      s.ev_contract.push_back(e1);
+    }
+    HIP_TRY(hipEventRecord(s.ev_contract[2 * pi], st));
+    if (mixed)
+      HIP_TRY(launch_contract_mixed(p.tile.wm, p.tile.wn, tasks, tiles + ps.tile0, ps.tile1 - ps.tile0, ws, st));
+    else
+      HIP_TRY(launch_contract_f64(p.tile.wm, p.tile.wn, tasks, tiles + ps.tile0, ps.tile1 - ps.tile0, ws, st));
+    HIP_TRY(hipEventRecord(s.ev_contract[2 * pi + 1], st));
+    s.n_contract++;
+    for (auto& ph : ps.red_by_phase) {
+      HIP_TRY(launch_reduce(p.tile.wm, p.tile.wn, tasks, reds, items + item_pos, (int)ph.size(), ws, st));
+      item_pos += ph.size();
+    }
+  }
+  const int nb = p.n_bf, na = p.n_aux;
+  HIP_TRY(launch_symmetrize(out + p.off_S, nb, st));
+  HIP_TRY(launch_symmetrize(out + p.off_T, nb, st));
+  HIP_TRY(launch_symmetrize(out + p.off_V, nb, st));
+  HIP_TRY(launch_symmetrize(out + p.off_PQ, na, st));
+  if (s.want_chol && na > 0)
+    HIP_TRY(launch_cholesky(out + p.off_PQ, out + p.off_L, na, (int*)(base + L.status), st));
+  HIP_TRY(hipEventRecord(s.ev_kernels_done, st));
+  return PS_OK;
+}
+
+size_t output_bytes(const Plan& p, const ps_job& job) {
+  const size_t nb2 = (size_t)p.n_bf * p.n_bf * 8, na2 = (size_t)p.n_aux * p.n_aux * 8;
+  size_t b = 0;
+  if (job.S) b += nb2;
+  if (job.T) b += nb2;
+  if (job.V) b += nb2;
+  if (job.PQ) b += na2;
+  if (job.PQ_chol) b += na2;
+  if (job.abP) b += (size_t)p.n_aux * nb2;
+  return b;
+}
+
+// Copy the requested outputs to the caller's buffers (enqueued on the slot's stream).  With a host
+// bounce buffer (pinned), host outputs land there first, packed in S, T, V, PQ, PQ_chol, abP order.
+int32_t enqueue_outputs(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, const ps_job& job, char* host_bounce) {
+  char* base = (char*)s.arena;
+  const double* out = (const double*)(base + L.out);
+  const bool dev = job.out_location == PS_OUT_DEVICE;
+  hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  const size_t nb2 = (size_t)p.n_bf * p.n_bf * 8, na2 = (size_t)p.n_aux * p.n_aux * 8;
+  struct {
+    double* dst;
+    int64_t off;
+    size_t bytes;
+  } outs[6] = {{job.S, p.off_S, nb2},   {job.T, p.off_T, nb2},     {job.V, p.off_V, nb2},
+               {job.PQ, p.off_PQ, na2}, {job.PQ_chol, p.off_L, na2}, {job.abP, p.off_abP, (size_t)p.n_aux * nb2}};
+  size_t bo = 0;
+  for (auto& o : outs) {
+    if (!o.dst || !o.bytes) continue;
+    void* dst = (!dev && host_bounce) ? (void*)(host_bounce + bo) : (void*)o.dst;
+    HIP_TRY(hipMemcpyAsync(dst, out + o.off, o.bytes, kind, s.stream));
+    bo += o.bytes;
+  }
+  HIP_TRY(hipMemcpyAsync((char*)s.pinned + L.status, base + L.status, sizeof(int), hipMemcpyDeviceToHost, s.stream));
+  HIP_TRY(hipEventRecord(s.ev_end, s.stream));
+  return PS_OK;
+}
+
+int32_t bind_slot(ps_ctx* ctx, Slot& s, const Plan& plan, const Layout& L, size_t extra_pinned, bool want_chol) {
+  int32_t rc = ensure_arena(ctx, s, L.total);
+  if (rc) return rc;
+  rc = ensure_pinned(ctx, s, L.meta_end + extra_pinned);
+  if (rc) return rc;
+  s.want_chol = want_chol;
+  stage_meta(plan, L, (char*)s.arena, (char*)s.pinned);
+  return PS_OK;
+}
+
+int32_t plan_job(ps_ctx* ctx, const ps_job* job, Plan& plan, Layout& L) {
+  std::string err;
+  int32_t rc = build_plan(job, ctx->shape, ctx->ksplit, ctx->budget, &plan, &err);
+  if (rc) {
+    ctx->err = err;
+    return rc;
+  }
+  compute_layout(plan, L);
+  if (L.total > ctx->budget) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "job needs %.2f GB of device memory, budget is %.2f GB", L.total / 1e9,
+             ctx->budget / 1e9);
+    ctx->err = buf;
+    return PS_E_NOMEM;
+  }
+  return PS_OK;
+}
+
+int32_t prepare_slot(ps_ctx* ctx, Slot& s, const ps_job* job, Plan& plan, Layout& L) {
+  int32_t rc = plan_job(ctx, job, plan, L);
+  if (rc) return rc;
+  return bind_slot(ctx, s, plan, L, 0, job->PQ_chol != nullptr);
+}
+
+int32_t finish_stats(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, ps_job_stats* st, double total_ms,
+                     double queue_ms) {
+  int status = *(int*)((char*)s.pinned + L.status);
+  if (st) {
+    std::memset(st, 0, sizeof *st);
+    st->n_grids = (int64_t)p.grids.size();
+    st->n_points = p.n_points;
+    st->pair_points = p.pair_points;
+    st->contract_flops = p.contract_flops;
+    st->issued_flops = p.issued_flops;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, s.ev_start, s.ev_kernels_done) == hipSuccess) st->device_ms = ms;
+    double cms = 0.0;
+    for (int i = 0; i < s.n_contract; ++i) {
+      float m2 = 0.0f;
+      if (hipEventElapsedTime(&m2, s.ev_contract[2 * i], s.ev_contract[2 * i + 1]) == hipSuccess) cms += m2;
+    }
+    st->contract_ms = cms;
+    st->total_ms = total_ms;
+    st->queue_ms = queue_ms;
+  }
+  if (s.want_chol && status) {
+    ctx->err = "(P|Q) is not positive definite";
+    return PS_E_NOT_PD;
+  }
+  return PS_OK;
+}
+
+int32_t slot_init(ps_ctx* ctx, Slot& s, hipStream_t stream) {
+  s.own_stream = stream == nullptr;
+  if (s.own_stream) {
+    HIP_TRY(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+  } else {
+    s.stream = stream;
+  }
+  HIP_TRY(hipEventCreate(&s.ev_start));
+  HIP_TRY(hipEventCreate(&s.ev_kernels_done));
+  HIP_TRY(hipEventCreate(&s.ev_end));
+  return PS_OK;
+}
+
+void slot_free(Slot& s) {
+  if (s.stream) (void)hipStreamSynchronize(s.stream);
+  if (s.arena) (void)hipFree(s.arena);
+  if (s.pinned) (void)hipHostFree(s.pinned);
+  for (auto e : s.ev_contract) (void)hipEventDestroy(e);
+  if (s.ev_start) (void)hipEventDestroy(s.ev_start);
+  if (s.ev_kernels_done) (void)hipEventDestroy(s.ev_kernels_done);
+  if (s.ev_end) (void)hipEventDestroy(s.ev_end);
+  if (s.own_stream && s.stream) (void)hipStreamDestroy(s.stream);
+  s = Slot();
+}
+
+}  // namespace psint
+
+using namespace psint;
+
+extern "C" {
+
+const char* ps_status_string(int32_t status) {
+  switch (status) {
+    case PS_OK: return "ok";
+    case PS_E_INVALID: return "invalid input";
+    case PS_E_UNSUPPORTED: return "unsupported input";
+    case PS_E_NOMEM: return "job exceeds the device-memory budget";
+    case PS_E_DEVICE: return "device error";
+    case PS_E_NOT_PD: return "(P|Q) not positive definite";
+    case PS_E_TIMEOUT: return "timeout";
+    case PS_E_QUEUE_FULL: return "queue full";
+    case PS_E_NOT_FOUND: return "unknown ticket";
+    default: return "unknown status";
+  }
+}
+
+const char* ps_last_error(ps_ctx* ctx) {
+  static thread_local std::string none = "";
+  return ctx ? ctx->err.c_str() : none.c_str();
+}
+
+int32_t ps_create(int32_t hip_device, size_t hbm_budget_bytes, void* stream, ps_ctx** out) {
+  if (!out) return PS_E_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return PS_E_DEVICE;
+  if (hipSetDevice(hip_device) != hipSuccess) return PS_E_DEVICE;
+  ps_ctx* ctx = new ps_ctx();
+  ctx->device = hip_device;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    delete ctx;
+    return PS_E_DEVICE;
+  }
+  ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)fr);
+  ctx->user_stream = (hipStream_t)stream;
+  int32_t rc = slot_init(ctx, ctx->sync_slot, (hipStream_t)stream);
+  if (rc) {
+    delete ctx;
+    return rc;
+  }
+  *out = ctx;
+  return PS_OK;
+}
+
+int32_t ps_destroy(ps_ctx* ctx) {
+  if (!ctx) return PS_E_INVALID;
+  serve_shutdown(ctx);
+  (void)hipSetDevice(ctx->device);
+  slot_free(ctx->sync_slot);
+  delete ctx;
+  return PS_OK;
+}
+
+int32_t ps_set_tiling(ps_ctx* ctx, int32_t wm, int32_t wn, int32_t ksplit) {
+  if (!ctx) return PS_E_INVALID;
+  if (wm == 0 && wn == 0) {
+    wm = 4;
+    wn = 4;
+  }
+  if (!((wm == 2 || wm == 4) && (wn == 2 || wn == 4)) || ksplit < 0) {
+    ctx->err = "tiling: wm, wn in {2, 4}, ksplit >= 0";
+    return PS_E_INVALID;
+  }
+  ctx->shape.wm = wm;
+  ctx->shape.wn = wn;
+  ctx->ksplit = ksplit;
+  return PS_OK;
+}
+
+int32_t ps_compute(ps_ctx* ctx, const ps_job* job, ps_job_stats* st) {
+  if (!ctx) return PS_E_INVALID;
+  auto t0 = std::chrono::steady_clock::now();
+  if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
+  Slot& s = ctx->sync_slot;
+  Plan plan;
+  Layout L;
+  int32_t rc = prepare_slot(ctx, s, job, plan, L);
+  if (rc) return rc;
+  rc = enqueue_job(ctx, s, plan, L);
+  if (rc) return rc;
+  rc = enqueue_outputs(ctx, s, plan, L, *job);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(s.stream));
+  double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return finish_stats(ctx, s, plan, L, st, ms, 0.0);
+}
+
+int32_t ps_plan_work(ps_ctx* ctx, const ps_job* job, double* pair_points, int64_t* n_grids, int64_t* n_points,
+                     size_t* device_bytes) {
+  // ctx may be NULL: host-only planning with the default tiling and an unbounded budget
+  Plan plan;
+  std::string err;
+  TileShape shape = ctx ? ctx->shape : TileShape();
+  int32_t rc = build_plan(job, shape, ctx ? ctx->ksplit : 0, ctx ? ctx->budget : ((size_t)1 << 62), &plan, &err);
+  if (rc) {
+    if (ctx) ctx->err = err;
+    return rc;
+  }
+  Layout L;
+  compute_layout(plan, L);
+  if (pair_points) *pair_points = plan.pair_points;
+  if (n_grids) *n_grids = (int64_t)plan.grids.size();
+  if (n_points) *n_points = plan.n_points;
+  if (device_bytes) *device_bytes = L.total;
+  return PS_OK;
+}
+
+int32_t ps_grid_points(ps_ctx* ctx, const ps_atom* atoms, int32_t n_atoms, int32_t A, int32_t B, int32_t C,
+                       const ps_grid_spec* spec, double* xyzw, int64_t* n_points) {
+  if (!ctx || !atoms || !spec || !n_points) return PS_E_INVALID;
+  GridHost g;
+  std::string err;
+  int32_t rc = build_grid(atoms, n_atoms, A, B, C, *spec, &g, &err);
+  if (rc) {
+    ctx->err = err;
+    return rc;
+  }
+  *n_points = g.dev.npts;
+  if (!xyzw) return PS_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
+  std::vector<double> lines;
+  g.dev.lines = 0;
+  lines.insert(lines.end(), g.mu.begin(), g.mu.end());
+  lines.insert(lines.end(), g.nu.begin(), g.nu.end());
+  lines.insert(lines.end(), g.phi.begin(), g.phi.end());
+  g.dev.gl = (int)lines.size();
+  double x[16], w[16];
+  gauss_legendre(g.dev.q, x, w);
+  lines.insert(lines.end(), x, x + g.dev.q);
+  lines.insert(lines.end(), w, w + g.dev.q);
+  double *dl = nullptr, *dp = nullptr;
+  hipStream_t st = ctx->sync_slot.stream;
+  HIP_TRY(hipMalloc(&dl, lines.size() * 8));
+  hipError_t e = hipMalloc(&dp, (size_t)g.dev.npts * 4 * 8);
+  if (e != hipSuccess) {
+    (void)hipFree(dl);
+    ctx->err = hipGetErrorString(e);
+    return PS_E_DEVICE;
+  }
+  e = hipMemcpyAsync(dl, lines.data(), lines.size() * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_grid_points(g.dev, dl, atoms[A].xyz, dp, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(xyzw, dp, (size_t)g.dev.npts * 32, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(dl);
+  (void)hipFree(dp);
+  if (e != hipSuccess) {
+    ctx->err = hipGetErrorString(e);
+    return PS_E_DEVICE;
+  }
+  return PS_OK;
+}
+
+int32_t ps_eval_function(ps_ctx* ctx, int32_t what, const ps_sto* fn, const double* center, int64_t npts,
+                         const double* x, const double* y, const double* z, double* out) {
+  if (!ctx || !fn || !center || (npts > 0 && (!x || !y || !z || !out)) || what < 0 || what > 2)
+    return PS_E_INVALID;
+  if (fn->n < 1 || fn->l < 0 || fn->l >= fn->n || fn->m < -fn->l || fn->m > fn->l || !(fn->zeta > 0.0))
+    return PS_E_INVALID;
+  if (fn->l > LMAX || fn->n > NMAX) return PS_E_UNSUPPORTED;
+  if (npts == 0) return PS_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
+  ShellDev sh;
+  sh.zeta = fn->zeta;
+  sh.n = fn->n;
+  sh.l = fn->l;
+  sh.norm = std::pow(2.0 * fn->zeta, fn->n + 0.5) / std::sqrt(factorial(2 * fn->n));
+  sh.pre = 4.0 * kPi / (2.0 * fn->l + 1.0) * sh.norm * std::pow(fn->zeta, -(fn->n + 1.0));
+  sh.m_off = 0;
+  sh.nm = 1;
+  MEntry me;
+  int am = std::abs(fn->m);
+  me.f = std::sqrt((2.0 * fn->l + 1.0) / (4.0 * kPi) * factorial(fn->l - am) / factorial(fn->l + am)) *
+         (am ? std::sqrt(2.0) : 1.0);
+  me.m = fn->m;
+  me.col = 0;
+  double* d = nullptr;
+  hipStream_t st = ctx->sync_slot.stream;
+  HIP_TRY(hipMalloc(&d, (size_t)npts * 4 * 8));
+  hipError_t e = hipMemcpyAsync(d, x, npts * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(d + npts, y, npts * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(d + 2 * npts, z, npts * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_eval_points(what, sh, me, center, d, d + npts, d + 2 * npts, npts, d + 3 * npts, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d + 3 * npts, npts * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d);
+  if (e != hipSuccess) {
+    ctx->err = hipGetErrorString(e);
+    return PS_E_DEVICE;
+  }
+  return PS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+// Context and per-job device slots (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/psint.h"
+#include "plan.h"
+
+namespace psint {
+
+// Device resources of one in-flight job: stream, arena (tables + arrays + workspace + outputs),
+// pinned staging for its tables, and timing events.
+struct Slot {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void* arena = nullptr;
+  size_t arena_size = 0;
+  void* pinned = nullptr;
+  size_t pinned_size = 0;
+  hipEvent_t ev_start = nullptr, ev_kernels_done = nullptr, ev_end = nullptr;
+  std::vector<hipEvent_t> ev_contract;
+  int n_contract = 0;
+  bool want_chol = false;
+};
+
+struct ServeState;
+
+}  // namespace psint
+
+struct ps_ctx {
+  int device = 0;
+  size_t budget = 0;
+  hipStream_t user_stream = nullptr;
+  std::string err;
+  psint::TileShape shape;
+  int ksplit = 0;
+  psint::Slot sync_slot;
+  psint::ServeState* serve = nullptr;  // created by the first ps_submit, freed by ps_destroy
+};
+
+namespace psint {
+
+struct Layout;
+int32_t slot_init(ps_ctx* ctx, Slot& s, hipStream_t stream);
+void slot_free(Slot& s);
+void serve_shutdown(ps_ctx* ctx);
+
+}  // namespace psint

@@ -1,0 +1,39 @@
+// Job preparation and enqueueing shared by the synchronous and serving paths (internal).
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "ctx.h"
+
+namespace psint {
+
+// Device layout of one planned job: tables, then arrays, workspace and the FP64 output buffer.
+struct Layout {
+  size_t grids, lines, shells, ments, wcols, segs, tasks, tiles, reds, ints, items, status;
+  size_t meta_end;
+  size_t arrays, ws, out;
+  size_t total;
+  std::vector<int32_t> items_host;  // reduce item ids, concatenated per (pass, phase)
+};
+
+void compute_layout(const Plan& p, Layout& L);
+// Plan the job and size its device layout (PS_E_NOMEM beyond the budget).
+int32_t plan_job(ps_ctx* ctx, const ps_job* job, Plan& plan, Layout& L);
+// Size the slot's arena and pinned staging (plus `extra_pinned` bytes) and stage the tables.
+int32_t bind_slot(ps_ctx* ctx, Slot& s, const Plan& plan, const Layout& L, size_t extra_pinned, bool want_chol);
+// plan_job + bind_slot.
+int32_t prepare_slot(ps_ctx* ctx, Slot& s, const ps_job* job, Plan& plan, Layout& L);
+// Enqueue all device work of a prepared job on the slot's stream.
+int32_t enqueue_job(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L);
+// Enqueue the output copies (to the caller's buffers, or to `host_bounce` for host outputs when
+// non-null) and the end event.
+int32_t enqueue_outputs(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, const ps_job& job,
+                        char* host_bounce = nullptr);
+// Fill the stats of a completed job and turn the Cholesky status into a return code.
+int32_t finish_stats(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, ps_job_stats* st, double total_ms,
+                     double queue_ms);
+int32_t ensure_pinned(ps_ctx* ctx, Slot& s, size_t bytes);
+int32_t ensure_arena(ps_ctx* ctx, Slot& s, size_t bytes);
+size_t output_bytes(const Plan& p, const ps_job& job);
+
+}  // namespace psint

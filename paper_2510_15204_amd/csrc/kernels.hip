@@ -1,0 +1,895 @@
+// gfx950 kernels for prolate-spheroidal quadrature of Slater integrals.
+//
+//   eval_kernel      one thread per grid point: PS coordinates -> focus-relative displacements and
+//                    weight (FP64), then Slater values, kinetic values, w * aux potentials or weight
+//                    columns into chunked-SoA arrays (coalesced 128-byte lines per column chunk).
+//   contract_f64     C[(u,v)][y] = sum_g U[u][g] V[v][g] Y[y][g]: the pair product is formed in
+//                    registers from LDS-staged columns and fed to v_mfma_f64_16x16x4; each
+//                    work-group owns one (pair-rows x columns) tile over a range of point chunks and
+//                    writes an FP64 partial tile.
+//   reduce_kernel    sums the partial tiles of a tile in split order (deterministic) and scatters
+//                    into the FP64 output buffer, with an optional mirrored write.
+//   symmetrize / cholesky / fill / copy helpers.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "psint_internal.h"
+
+namespace psint {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------------------------------------
+// Grid geometry.  Point g of grid G: cell c = g / q^3 with GL node indices (p, q, r); cells past
+// n_reg are the extra subcells of the 8 cells around the third centre (subcell 0 of each of those
+// 8 cells keeps the cell's own slot in the regular enumeration).
+// ------------------------------------------------------------------------------------------------
+struct Geo {
+  double w;
+  double d[3][3];  // displacement point - centre (A, B, C), global orientation
+  double r[3];
+};
+
+__device__ __forceinline__ void point_geo(const GridDev& G, const double* __restrict__ lines, int64_t g,
+                                          Geo& o) {
+  const int q = G.q, q2 = q * q, q3 = q2 * q;
+  const int64_t c = g / q3;
+  const int rem = (int)(g - c * q3);
+  const int ip = rem / q2, iq = (rem / q) % q, ir = rem % q;
+  int i, j, k, ns = 1, si = 0, sj = 0, sk = 0;
+  if (c < G.n_reg) {
+    const int64_t plane = (int64_t)G.nnu * G.nphi;
+    i = (int)(c / plane);
+    const int64_t r2 = c - (int64_t)i * plane;
+    j = (int)(r2 / G.nphi);
+    k = (int)(r2 - (int64_t)j * G.nphi);
+    if (G.split && (i == G.istar - 1 || i == G.istar) && (j == G.jstar - 1 || j == G.jstar) &&
+        (k == G.nphi - 1 || k == 0))
+      ns = G.nsp;
+  } else {
+    const int s3m = G.nsp * G.nsp * G.nsp - 1;
+    const int64_t e = c - G.n_reg;
+    const int which = (int)(e / s3m);
+    const int sub = (int)(e - (int64_t)which * s3m) + 1;
+    i = G.istar - 1 + (which >> 2);
+    j = G.jstar - 1 + ((which >> 1) & 1);
+    k = (which & 1) ? 0 : G.nphi - 1;
+    ns = G.nsp;
+    si = sub / (G.nsp * G.nsp);
+    sj = (sub / G.nsp) % G.nsp;
+    sk = sub % G.nsp;
+  }
+  const double* mu = lines + G.lines;
+  const double* nu = mu + G.nmu + 1;
+  const double* ph = nu + G.nnu + 1;
+  const double* glx = lines + G.gl;
+  const double* glw = glx + q;
+  const double inv = 1.0 / ns;
+  const double hm = (mu[i + 1] - mu[i]) * inv, hn = (nu[j + 1] - nu[j]) * inv, hp = (ph[k + 1] - ph[k]) * inv;
+  const double m = mu[i] + hm * (si + 0.5 * (1.0 + glx[ip]));
+  const double n = nu[j] + hn * (sj + 0.5 * (1.0 + glx[iq]));
+  const double f = ph[k] + hp * (sk + 0.5 * (1.0 + glx[ir]));
+  const double wq = (0.5 * hm * glw[ip]) * (0.5 * hn * glw[iq]) * (0.5 * hp * glw[ir]);
+  // half-angle forms keep distances to the foci free of cancellation
+  const double shh = sinh(0.5 * m);
+  const double s2 = shh * shh;
+  const double chh = sqrt(1.0 + s2);
+  double sn2, cs2, sf, cf;
+  sincos(0.5 * n, &sn2, &cs2);
+  sincos(f, &sf, &cf);
+  const double sh = 2.0 * shh * chh, ch = 1.0 + 2.0 * s2;
+  const double sn = 2.0 * sn2 * cs2, cs = (cs2 - sn2) * (cs2 + sn2);
+  const double a = G.a;
+  o.w = wq * a * a * a * sh * sn * (sh * sh + sn * sn);
+  const double rho = a * sh * sn;
+  const double lx = rho * cf, ly = rho * sf;
+  const double lz[3] = {a * (2.0 * s2 * cs - 2.0 * sn2 * sn2), a * (2.0 * s2 * cs + 2.0 * cs2 * cs2),
+                        a * ch * cs - G.cz};
+  const double lxs[3] = {lx, lx, lx - G.cx};
+  o.r[0] = 2.0 * a * (s2 + sn2 * sn2);
+  o.r[1] = 2.0 * a * (s2 + cs2 * cs2);
+  o.r[2] = sqrt(lxs[2] * lxs[2] + ly * ly + lz[2] * lz[2]);
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    o.d[t][0] = lxs[t] * G.ex[0] + ly * G.ey[0] + lz[t] * G.ez[0];
+    o.d[t][1] = lxs[t] * G.ex[1] + ly * G.ey[1] + lz[t] * G.ez[1];
+    o.d[t][2] = lxs[t] * G.ex[2] + ly * G.ey[2] + lz[t] * G.ez[2];
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Slater radial parts and the Coulomb potential of an auxiliary Slater function.
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ double ipow(double x, int k) {
+  double r = 1.0;
+  for (int i = 0; i < k; ++i) r *= x;
+  return r;
+}
+
+__constant__ double kFact[24] = {1.0,
+                                 1.0,
+                                 2.0,
+                                 6.0,
+                                 24.0,
+                                 120.0,
+                                 720.0,
+                                 5040.0,
+                                 40320.0,
+                                 362880.0,
+                                 3628800.0,
+                                 39916800.0,
+                                 479001600.0,
+                                 6227020800.0,
+                                 87178291200.0,
+                                 1307674368000.0,
+                                 20922789888000.0,
+                                 355687428096000.0,
+                                 6402373705728000.0,
+                                 121645100408832000.0,
+                                 2432902008176640000.0,
+                                 51090942171709440000.0,
+                                 1124000727777607680000.0,
+                                 25852016738884976640000.0};
+
+// Integer-order incomplete gamma functions from the terms t_j = x^j / j!:
+//   Gamma(k, x) = (k-1)! e^-x sum_{j<k} t_j,   gamma(k, x) = (k-1)! e^-x sum_{j>=k} t_j,
+// the tail summed directly while x < k + 1 (no cancellation), else gamma = (k-1)! (1 - e^-x head).
+__device__ __forceinline__ void inc_gamma_pair(int k_lo, int k_up, double x, double ex, double* lower,
+                                               double* upper) {
+  // upper: head sum to k_up - 1
+  double t = 1.0, head = 1.0;
+  for (int j = 1; j < k_up; ++j) {
+    t *= x / j;
+    head += t;
+  }
+  *upper = kFact[k_up - 1] * ex * head;
+  // lower of order k_lo (> k_up)
+  double t2 = 1.0, h2 = 1.0;
+  for (int j = 1; j < k_lo; ++j) {
+    t2 *= x / j;
+    h2 += t2;
+  }
+  if (x < k_lo + 1.0) {
+    double tail = 0.0;
+    double tj = t2 * x / k_lo;  // t_{k_lo}
+    for (int j = k_lo; j < k_lo + 200; ++j) {
+      tail += tj;
+      if (tj < 1e-17 * tail) break;
+      tj *= x / (j + 1);
+    }
+    *lower = kFact[k_lo - 1] * ex * tail;
+  } else {
+    *lower = kFact[k_lo - 1] * (1.0 - ex * h2);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Evaluation kernel.  Real solid harmonics of the unit displacement by the Cartesian recurrences
+//   C_l^l = (2l-1)(x C_{l-1}^{l-1} - y S_{l-1}^{l-1}),  S_l^l = (2l-1)(y C_{l-1}^{l-1} + x S_{l-1}^{l-1}),
+//   C_l^{l-1} = (2l-1) z C_{l-1}^{l-1},  (l-m) C_l^m = (2l-1) z C_{l-1}^m - (l+m-1) C_{l-2}^m,
+// (same for S), which give P_l^m(cos t) cos(m phi) and sin(m phi) without the Condon-Shortley phase;
+// Y_lm = f * C_l^m (m >= 0) or f * S_l^|m| (m < 0) with f from the host.
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void eval_kernel(const SegDev* __restrict__ segs, int nseg,
+                                                   const GridDev* __restrict__ grids,
+                                                   const double* __restrict__ lines,
+                                                   const ShellDev* __restrict__ shells,
+                                                   const MEntry* __restrict__ ments,
+                                                   const WColDev* __restrict__ wcols) {
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].block0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const SegDev& S = segs[lo];
+  const GridDev& G = grids[S.grid];
+  const int64_t g = (b - S.block0) * 256 + threadIdx.x;
+  T* __restrict__ out0 = (T*)S.arr0;
+  T* __restrict__ out1 = (T*)S.arr1;
+  const int64_t base = (g / KC) * (int64_t)S.nf * KC + (g % KC);
+  if (g >= G.npts) {  // padding points: every column exactly zero
+    if (S.mode == EV_WEIGHTS) {
+      for (int it = 0; it < S.n_items; ++it) out0[base + (int64_t)wcols[S.item_off + it].col * KC] = (T)0;
+    } else {
+      for (int s = S.item_off; s < S.item_off + S.n_items; ++s) {
+        const ShellDev sh = shells[s];
+        for (int e = 0; e < sh.nm; ++e) {
+          const int64_t o = base + (int64_t)ments[sh.m_off + e].col * KC;
+          out0[o] = (T)0;
+          if (S.mode == EV_CHI_KIN) out1[o] = (T)0;
+        }
+      }
+    }
+    return;
+  }
+  Geo geo;
+  point_geo(G, lines, g, geo);
+  if (S.mode == EV_WEIGHTS) {
+    for (int it = 0; it < S.n_items; ++it) {
+      const WColDev W = wcols[S.item_off + it];
+      double v;
+      if (W.kind == 0) v = geo.w;
+      else if (W.kind == 1) v = 1.0;
+      else {
+        double pot = W.zA / geo.r[0] + W.zB / geo.r[1];
+        if (W.zC != 0.0) pot += W.zC / geo.r[2];
+        v = -geo.w * pot;
+      }
+      out0[base + (int64_t)W.col * KC] = (T)v;
+    }
+    return;
+  }
+  // select the segment's centre without dynamic indexing (keeps Geo in registers)
+  const int cen = S.centre;
+  const double r = cen == 0 ? geo.r[0] : (cen == 1 ? geo.r[1] : geo.r[2]);
+  const double dx = cen == 0 ? geo.d[0][0] : (cen == 1 ? geo.d[1][0] : geo.d[2][0]);
+  const double dy = cen == 0 ? geo.d[0][1] : (cen == 1 ? geo.d[1][1] : geo.d[2][1]);
+  const double dz = cen == 0 ? geo.d[0][2] : (cen == 1 ? geo.d[1][2] : geo.d[2][2]);
+  const double ir = 1.0 / r;
+  const double x = dx * ir, y = dy * ir, z = dz * ir;
+  double Cm2[LMAX + 1], Sm2[LMAX + 1], Cm1[LMAX + 1], Sm1[LMAX + 1], C[LMAX + 1], Sv[LMAX + 1];
+#pragma unroll
+  for (int m = 0; m <= LMAX; ++m) Cm2[m] = Sm2[m] = Cm1[m] = Sm1[m] = C[m] = Sv[m] = 0.0;
+  int lmax_seg = 0;
+  for (int l = 0; l <= LMAX; ++l)
+    if (S.l_off[l + 1] > S.l_off[l]) lmax_seg = l;
+  for (int l = 0; l <= lmax_seg; ++l) {
+    if (l == 0) {
+      C[0] = 1.0;
+      Sv[0] = 0.0;
+    } else {
+      const double tl = 2.0 * l - 1.0;
+#pragma unroll
+      for (int m = 0; m <= LMAX; ++m) {
+        double cn = 0.0, sn = 0.0;
+        if (m == l) {
+          if (m >= 1) {
+            cn = tl * (x * Cm1[m >= 1 ? m - 1 : 0] - y * Sm1[m >= 1 ? m - 1 : 0]);
+            sn = tl * (y * Cm1[m >= 1 ? m - 1 : 0] + x * Sm1[m >= 1 ? m - 1 : 0]);
+          }
+        } else if (m == l - 1) {
+          cn = tl * z * Cm1[m];
+          sn = tl * z * Sm1[m];
+        } else if (m < l - 1) {
+          const double inv = 1.0 / (double)(l - m);
+          cn = (tl * z * Cm1[m] - (l + m - 1.0) * Cm2[m]) * inv;
+          sn = (tl * z * Sm1[m] - (l + m - 1.0) * Sm2[m]) * inv;
+        }
+        C[m] = cn;
+        Sv[m] = sn;
+      }
+    }
+    // shells with this l
+    for (int s = S.l_off[l]; s < S.l_off[l + 1]; ++s) {
+      const ShellDev sh = shells[s];
+      const double ex = exp(-sh.zeta * r);
+      double rad, kin = 0.0;
+      if (S.mode == EV_POT_W) {
+        const double xx = sh.zeta * r;
+        double lower, upper;
+        inc_gamma_pair(sh.n + l + 2, sh.n - l + 1, xx, ex, &lower, &upper);
+        const double ixx = 1.0 / xx;
+        rad = geo.w * sh.pre * (ipow(ixx, l + 1) * lower + ipow(xx, l) * upper);
+      } else {
+        rad = sh.norm * ipow(r, sh.n - 1) * ex;
+        if (S.mode == EV_CHI_KIN) {
+          const double f = sh.zeta * sh.zeta - 2.0 * sh.zeta * sh.n * ir +
+                           (sh.n * (sh.n - 1.0) - l * (l + 1.0)) * ir * ir;
+          kin = -0.5 * f * rad;
+        }
+      }
+      for (int e = 0; e < sh.nm; ++e) {
+        const MEntry me = ments[sh.m_off + e];
+        const int am = me.m < 0 ? -me.m : me.m;
+        double Yh = 0.0;
+#pragma unroll
+        for (int mm = 0; mm <= LMAX; ++mm)
+          if (mm == am) Yh = me.m < 0 ? Sv[mm] : C[mm];
+        Yh *= me.f;
+        const int64_t o = base + (int64_t)me.col * KC;
+        out0[o] = (T)(rad * Yh);
+        if (S.mode == EV_CHI_KIN) out1[o] = (T)(kin * Yh);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m <= LMAX; ++m) {
+      Cm2[m] = Cm1[m];
+      Sm2[m] = Sm1[m];
+      Cm1[m] = C[m];
+      Sm1[m] = Sv[m];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Contraction kernels.  256 threads = 4 waves in 2 x 2; wave (wm, wn) owns WM x WN MFMA blocks of
+// 16 x 16.  Points are consumed in stages of SC storage chunks (SC * 16 points).  Each stage's U, V
+// and Y columns sit in LDS as rows of SC * 16 values padded by 4 (bank-conflict-free operand reads);
+// two LDS buffers alternate, so one barrier per stage suffices: while the MFMAs of stage s run on one
+// buffer, the registers holding stage s+1 (loaded during stage s-1) are written to the other buffer
+// and the loads of stage s+2 are issued, interleaved between the MFMA steps.
+//
+// Operand layouts (probed on gfx950): A lane l = A[l%16][l/16], B lane l = B[l/16][l%16];
+// v_mfma_f64_16x16x4 result register r of lane l = D[4r + l/16][l%16];
+// v_mfma_f32_16x16x4f32 result register r of lane l = D[4(l/16) + r][l%16].
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+struct Vec2;  // 16-byte global loads
+template <>
+struct Vec2<double> {
+  typedef double2 type;
+  static constexpr int N = 2;
+};
+template <>
+struct Vec2<float> {
+  typedef float4 type;
+  static constexpr int N = 4;
+};
+
+template <typename T, int WM, int WN, int SC>
+struct ContractCfg {
+  static constexpr int BM = 32 * WM, BN = 32 * WN;
+  static constexpr int KS = SC * KC;            // points per stage
+  static constexpr int LDK = KS + 4;            // padded LDS row
+  static constexpr int MAXUV = BM + 8;
+  static constexpr int ROWS = MAXUV + BN;
+  static constexpr int VN = Vec2<T>::N;         // values per 16-byte load
+  static constexpr int PER_ROW = KC / VN;       // loads per row per storage chunk
+  static constexpr int NPRE = (ROWS * SC * PER_ROW + 255) / 256;
+  static constexpr int LDS_BYTES = 2 * ROWS * LDK * (int)sizeof(T);
+};
+
+template <typename T, int WM, int WN, int SC>
+__device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, const TileDev& t, T* __restrict__ lds,
+                                              double* __restrict__ ws) {
+  typedef ContractCfg<T, WM, WN, SC> Cf;
+  constexpr int BM = Cf::BM, BN = Cf::BN, LDK = Cf::LDK, MAXUV = Cf::MAXUV, ROWS = Cf::ROWS;
+  constexpr int VN = Cf::VN, PER_ROW = Cf::PER_ROW, NPRE = Cf::NPRE, KS = Cf::KS;
+  typedef typename Vec2<T>::type V2;
+  constexpr bool F64 = sizeof(T) == 8;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int kl = lane >> 4;
+  T* buf[2] = {lds, lds + ROWS * LDK};
+
+  // Y rows past np stay zero in both buffers
+  for (int e = tid; e < (BN - t.np) * LDK; e += 256) {
+    buf[0][(MAXUV + t.np) * LDK + e] = (T)0;
+    buf[1][(MAXUV + t.np) * LDK + e] = (T)0;
+  }
+
+  int offU[WM], offV[WM];
+  bool valid[WM];
+#pragma unroll
+  for (int mb = 0; mb < WM; ++mb) {
+    const int row = wm * 16 * WM + mb * 16 + (lane & 15);
+    valid[mb] = row < t.nrows;
+    int u = t.ulo, v = t.vlo;
+    if (valid[mb]) {
+      u = Tk.pairs[2 * (t.row0 + row)];
+      v = Tk.pairs[2 * (t.row0 + row) + 1];
+    }
+    offU[mb] = (u - t.ulo) * LDK + kl;
+    offV[mb] = (t.nu + v - t.vlo) * LDK + kl;
+  }
+  int offY[WN];
+#pragma unroll
+  for (int nb = 0; nb < WN; ++nb) offY[nb] = (MAXUV + wn * 16 * WN + nb * 16 + (lane & 15)) * LDK + kl;
+
+  // staging map: a stage is SC chunks; chunk j's three runs (U, V, Y columns) concatenated
+  const T* __restrict__ Ub = (const T*)Tk.U + (int64_t)t.ulo * KC;
+  const T* __restrict__ Vb = (const T*)Tk.V + (int64_t)t.vlo * KC;
+  const T* __restrict__ Yb = (const T*)Tk.Y + (int64_t)(Tk.y0 + t.p0) * KC;
+  const int64_t sU = (int64_t)Tk.nfU * KC, sV = (int64_t)Tk.nfV * KC, sY = (int64_t)Tk.nfY * KC;
+  const int nUe = t.nu * PER_ROW, nUVe = nUe + t.nv * PER_ROW, tote = nUVe + t.np * PER_ROW;
+  const int64_t c_end = t.kc0 + t.nkc;
+  const int nstage = (int)((t.nkc + SC - 1) / SC);
+
+  V2 pre[NPRE];
+  auto load_stage = [&](int s) {
+#pragma unroll
+    for (int i = 0; i < NPRE; ++i) {
+      const int e = tid + 256 * i;
+      const int j = e / tote, e2 = e - j * tote;
+      const int64_t c = t.kc0 + (int64_t)s * SC + j;
+      if (j < SC && c < c_end) {
+        const V2* p;
+        if (e2 < nUe) p = (const V2*)(Ub + c * sU) + e2;
+        else if (e2 < nUVe) p = (const V2*)(Vb + c * sV) + (e2 - nUe);
+        else p = (const V2*)(Yb + c * sY) + (e2 - nUVe);
+        pre[i] = *p;
+      } else {
+        pre[i] = V2{};
+      }
+    }
+  };
+  auto store_part = [&](T* dst, int i) {
+    const int e = tid + 256 * i;
+    const int j = e / tote, e2 = e - j * tote;
+    if (j < SC) {
+      int row, kq;
+      if (e2 < nUe) { row = e2 / PER_ROW; kq = e2 - row * PER_ROW; }
+      else if (e2 < nUVe) { row = t.nu + (e2 - nUe) / PER_ROW; kq = (e2 - nUe) % PER_ROW; }
+      else { row = MAXUV + (e2 - nUVe) / PER_ROW; kq = (e2 - nUVe) % PER_ROW; }
+      T* d = dst + row * LDK + j * KC + kq * VN;
+      const T* v = (const T*)&pre[i];
+#pragma unroll
+      for (int q = 0; q < VN; ++q) d[q] = v[q];
+    }
+  };
+
+  typedef typename std::conditional<F64, d4_t, f4_t>::type Acc;
+  d4_t acc[WM][WN];
+#pragma unroll
+  for (int mb = 0; mb < WM; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < WN; ++nb) acc[mb][nb] = (d4_t){0.0, 0.0, 0.0, 0.0};
+
+  load_stage(0);
+#pragma unroll
+  for (int i = 0; i < NPRE; ++i) store_part(buf[0], i);
+  if (nstage > 1) load_stage(1);
+  __syncthreads();
+
+  constexpr int KSTEPS = KS / 4;
+  for (int s = 0; s < nstage; ++s) {
+    const T* cur = buf[s & 1];
+    T* nxt = buf[(s + 1) & 1];
+    const bool more = s + 1 < nstage;
+    Acc a32[WM][WN];
+    if constexpr (!F64) {
+#pragma unroll
+      for (int mb = 0; mb < WM; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < WN; ++nb) a32[mb][nb] = Acc{};
+    }
+#pragma unroll
+    for (int kk = 0; kk < KSTEPS; ++kk) {
+      T av[WM], bv[WN];
+#pragma unroll
+      for (int mb = 0; mb < WM; ++mb) {
+        const T p = cur[offU[mb] + 4 * kk] * cur[offV[mb] + 4 * kk];
+        av[mb] = valid[mb] ? p : (T)0;
+      }
+#pragma unroll
+      for (int nb = 0; nb < WN; ++nb) bv[nb] = cur[offY[nb] + 4 * kk];
+#pragma unroll
+      for (int mb = 0; mb < WM; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < WN; ++nb) {
+          if constexpr (F64)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+          else
+            a32[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb], bv[nb], a32[mb][nb], 0, 0, 0);
+        }
+      // spread the next stage's LDS writes over the MFMA steps
+      if (more) {
+#pragma unroll
+        for (int i = 0; i < NPRE; ++i)
+          if (i % KSTEPS == kk) store_part(nxt, i);
+      }
+    }
+    if constexpr (!F64) {
+      // flush this stage's FP32 partial sums into the FP64 accumulators
+#pragma unroll
+      for (int mb = 0; mb < WM; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < WN; ++nb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[mb][nb][r] += (double)a32[mb][nb][r];
+    }
+    if (s + 2 < nstage) load_stage(s + 2);
+    __syncthreads();
+  }
+  double* __restrict__ wt = ws + t.ws;
+#pragma unroll
+  for (int mb = 0; mb < WM; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < WN; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wm * 16 * WM + mb * 16 + (F64 ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r);
+        const int col = wn * 16 * WN + nb * 16 + (lane & 15);
+        wt[row * BN + col] = acc[mb][nb][r];
+      }
+}
+
+template <int WM, int WN, int SC>
+__global__ __launch_bounds__(256, 1) void contract_f64(const TaskDev* __restrict__ tasks,
+                                                       const TileDev* __restrict__ tiles,
+                                                       double* __restrict__ ws) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const TileDev t = tiles[blockIdx.x];
+  contract_body<double, WM, WN, SC>(tasks[t.task], t, (double*)smem, ws);
+}
+
+template <int WM, int WN, int SC>
+__global__ __launch_bounds__(256, 1) void contract_mixed(const TaskDev* __restrict__ tasks,
+                                                         const TileDev* __restrict__ tiles,
+                                                         double* __restrict__ ws) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const TileDev t = tiles[blockIdx.x];
+  contract_body<float, WM, WN, SC>(tasks[t.task], t, (float*)smem, ws);
+}
+
+// Sum the splits of each reduction item in order and scatter into the FP64 output buffer.
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void reduce_kernel(const TaskDev* __restrict__ tasks,
+                                                     const RedDev* __restrict__ reds,
+                                                     const int32_t* __restrict__ items,
+                                                     const double* __restrict__ ws) {
+  const RedDev R = reds[items[blockIdx.x]];
+  const TaskDev& T = tasks[R.task];
+  for (int e = threadIdx.x; e < BM * BN; e += 256) {
+    const int row = e % BM, col = e / BM;
+    if (row >= R.nrows || col >= R.np) continue;
+    double s = 0.0;
+    const double* p = ws + R.ws + row * BN + col;
+    for (int k = 0; k < R.nsplit; ++k) s += p[(int64_t)k * BM * BN];
+    const int u = T.pairs[2 * (R.row0 + row)], v = T.pairs[2 * (R.row0 + row) + 1];
+    const int y = T.y0 + R.p0 + col;
+    const int64_t ia = T.mapU[u], ib = T.mapV[v], ip = T.mapY[y];
+    const double val = T.alpha * s;
+    T.out[ia * T.s1 + ib * T.s2 + ip * T.s3] += val;
+    if (T.outm && !(T.skip_diag && ia == ib)) T.outm[ia * T.t1 + ib * T.t2 + ip * T.t3] += val;
+  }
+}
+
+__global__ void fill_kernel(double* __restrict__ p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// X <- (X + X^T) / 2 for an n x n matrix (upper-triangle threads write both halves).
+__global__ void symmetrize_kernel(double* __restrict__ X, int n) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    if (j <= i) continue;
+    const double s = 0.5 * (X[(int64_t)i * n + j] + X[(int64_t)j * n + i]);
+    X[(int64_t)i * n + j] = s;
+    X[(int64_t)j * n + i] = s;
+  }
+}
+
+// Blocked right-looking Cholesky in FP64, panel width CB = 32.  L starts as a copy of A.
+// chol_panel: factor the CB x CB diagonal block in LDS (a pivot not larger than 1e-14 times the
+// original diagonal entry of A sets *status and stops every later kernel).
+// chol_trsm: the panel rows below it, L21 <- A21 L11^-T.
+// chol_update: A22 <- A22 - L21 L21^T on the lower triangle, 64 x 64 tiles.
+constexpr int CB = 32;
+
+__global__ __launch_bounds__(256) void chol_panel(const double* __restrict__ A, double* __restrict__ L, int n, int k0,
+                                                  int* __restrict__ status) {
+  __shared__ double D[CB][CB + 1];
+  __shared__ int bad;
+  if (*status) return;
+  const int tid = threadIdx.x;
+  const int nb = min(CB, n - k0);
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int i = e / CB, j = e % CB;
+    D[i][j] = (i < nb && j < nb && j <= i) ? L[(int64_t)(k0 + i) * n + k0 + j] : 0.0;
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    if (tid == 0) {
+      const double d = D[k][k];
+      if (!(d > 1e-14 * A[(int64_t)(k0 + k) * n + k0 + k])) bad = 1;
+      else D[k][k] = sqrt(d);
+    }
+    __syncthreads();
+    if (bad) break;
+    const double piv = D[k][k];
+    if (tid > k && tid < nb) D[tid][k] /= piv;
+    __syncthreads();
+    for (int e = tid; e < CB * CB; e += 256) {
+      const int i = e / CB, j = e % CB;
+      if (j > k && i >= j && i < nb) D[i][j] -= D[i][k] * D[j][k];
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) *status = 1;
+    return;
+  }
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int i = e / CB, j = e % CB;
+    if (i < nb && j <= i) L[(int64_t)(k0 + i) * n + k0 + j] = D[i][j];
+  }
+}
+
+// Panel rows below the diagonal block: x D^T = a for each row.  Each wave solves two rows with one
+// entry per lane (lanes 0-31 one row, 32-63 the next); x_p is broadcast with a lane shuffle.
+__global__ __launch_bounds__(256) void chol_trsm(double* __restrict__ L, int n, int k0, const int* __restrict__ status) {
+  __shared__ double D[CB][CB + 1];
+  if (*status) return;
+  const int tid = threadIdx.x;
+  const int nb = min(CB, n - k0);
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int i = e / CB, j = e % CB;
+    D[i][j] = (i < nb && j < nb && j <= i) ? L[(int64_t)(k0 + i) * n + k0 + j] : 0.0;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6, half = lane >> 5, q = lane & 31;
+  const int first = k0 + nb + blockIdx.x * 64;
+  for (int r = 0; r < 64; r += 8) {
+    const int i = first + r + wave * 2 + half;
+    const bool live = i < n && q < nb;
+    double x = live ? L[(int64_t)i * n + k0 + q] : 0.0;
+    for (int p = 0; p < nb; ++p) {
+      if (q == p) x /= D[p][p];
+      const double xp = __shfl(x, (half << 5) + p, 64);
+      if (q > p) x -= xp * D[q][p];
+    }
+    if (live) L[(int64_t)i * n + k0 + q] = x;
+  }
+}
+
+__global__ __launch_bounds__(256) void chol_update(double* __restrict__ L, int n, int k0, const int* __restrict__ status) {
+  if (*status) return;
+  const int base = k0 + CB;
+  const int ti = blockIdx.x, tj = blockIdx.y;
+  if (tj > ti) return;
+  const int i0 = base + ti * 64, j0 = base + tj * 64;
+  __shared__ double Ri[64][CB + 1], Rj[64][CB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * CB; e += 256) {
+    const int r = e / CB, p = e % CB;
+    Ri[r][p] = (i0 + r < n) ? L[(int64_t)(i0 + r) * n + k0 + p] : 0.0;
+    Rj[r][p] = (j0 + r < n) ? L[(int64_t)(j0 + r) * n + k0 + p] : 0.0;
+  }
+  __syncthreads();
+  const int tr = tid / 16, tc = tid % 16;
+  double acc[4][4] = {};
+#pragma unroll 4
+  for (int p = 0; p < CB; ++p) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = Ri[tr * 4 + u][p];
+      b[u] = Rj[tc * 4 + u][p];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + tr * 4 + u, j = j0 + tc * 4 + v;
+      if (i < n && j <= i) L[(int64_t)i * n + j] -= acc[u][v];
+    }
+}
+
+__global__ void copy_lower_kernel(const double* __restrict__ A, double* __restrict__ L, int n, int zero_upper) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    if (zero_upper) {
+      if (j > i) L[e] = 0.0;
+    } else {
+      L[e] = A[e];
+    }
+  }
+}
+
+// Grid points for the inspection hook: xyzw[4 g + 0..3] = (x, y, z, w) in the global frame.
+__global__ void grid_points_kernel(GridDev G, const double* __restrict__ lines, double ax, double ay, double az,
+                                   double* __restrict__ xyzw) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= G.npts) return;
+  Geo geo;
+  point_geo(G, lines, g, geo);
+  xyzw[4 * g + 0] = ax + geo.d[0][0];
+  xyzw[4 * g + 1] = ay + geo.d[0][1];
+  xyzw[4 * g + 2] = az + geo.d[0][2];
+  xyzw[4 * g + 3] = geo.w;
+}
+
+// One function at arbitrary points (inspection hook): what 0 chi, 1 -1/2 lap chi, 2 potential.
+__global__ void eval_points_kernel(int what, ShellDev sh, MEntry me, double cx, double cy, double cz,
+                                   const double* __restrict__ X, const double* __restrict__ Y,
+                                   const double* __restrict__ Z, int64_t n, double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double dx = X[i] - cx, dy = Y[i] - cy, dz = Z[i] - cz;
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  const double ir = 1.0 / r;
+  const double x = dx * ir, y = dy * ir, z = dz * ir;
+  const int l = sh.l;
+  double Cm2[LMAX + 1] = {}, Sm2[LMAX + 1] = {}, Cm1[LMAX + 1] = {}, Sm1[LMAX + 1] = {}, C[LMAX + 1] = {},
+         Sv[LMAX + 1] = {};
+  for (int ll = 0; ll <= l; ++ll) {
+    if (ll == 0) {
+      C[0] = 1.0;
+      Sv[0] = 0.0;
+    } else {
+      const double tl = 2.0 * ll - 1.0;
+#pragma unroll
+      for (int m = 0; m <= LMAX; ++m) {
+        double cn = 0.0, sn = 0.0;
+        if (m == ll) {
+          if (m >= 1) {
+            cn = tl * (x * Cm1[m >= 1 ? m - 1 : 0] - y * Sm1[m >= 1 ? m - 1 : 0]);
+            sn = tl * (y * Cm1[m >= 1 ? m - 1 : 0] + x * Sm1[m >= 1 ? m - 1 : 0]);
+          }
+        } else if (m == ll - 1) {
+          cn = tl * z * Cm1[m];
+          sn = tl * z * Sm1[m];
+        } else if (m < ll - 1) {
+          cn = (tl * z * Cm1[m] - (ll + m - 1.0) * Cm2[m]) / (double)(ll - m);
+          sn = (tl * z * Sm1[m] - (ll + m - 1.0) * Sm2[m]) / (double)(ll - m);
+        }
+        C[m] = cn;
+        Sv[m] = sn;
+      }
+    }
+    if (ll < l) {
+#pragma unroll
+      for (int m = 0; m <= LMAX; ++m) {
+        Cm2[m] = Cm1[m];
+        Sm2[m] = Sm1[m];
+        Cm1[m] = C[m];
+        Sm1[m] = Sv[m];
+      }
+    }
+  }
+  const int am = me.m < 0 ? -me.m : me.m;
+  double Yh = 0.0;
+#pragma unroll
+  for (int mm = 0; mm <= LMAX; ++mm)
+    if (mm == am) Yh = me.m < 0 ? Sv[mm] : C[mm];
+  Yh *= me.f;
+  const double ex = exp(-sh.zeta * r);
+  double v;
+  if (what == 2) {
+    const double xx = sh.zeta * r;
+    double lower, upper;
+    inc_gamma_pair(sh.n + l + 2, sh.n - l + 1, xx, ex, &lower, &upper);
+    v = sh.pre * (ipow(1.0 / xx, l + 1) * lower + ipow(xx, l) * upper) * Yh;
+  } else {
+    const double rad = sh.norm * ipow(r, sh.n - 1) * ex;
+    v = rad * Yh;
+    if (what == 1)
+      v *= -0.5 * (sh.zeta * sh.zeta - 2.0 * sh.zeta * sh.n * ir + (sh.n * (sh.n - 1.0) - l * (l + 1.0)) * ir * ir);
+  }
+  out[i] = v;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Launch wrappers (host).
+// ------------------------------------------------------------------------------------------------
+hipError_t launch_eval(bool fp32, const SegDev* segs, int nseg, int64_t nblocks, const GridDev* grids,
+                       const double* lines, const ShellDev* shells, const MEntry* ments, const WColDev* wcols,
+                       hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(eval_kernel<float>, dim3((unsigned)nblocks), dim3(256), 0, st, segs, nseg, grids, lines,
+                       shells, ments, wcols);
+  else
+    hipLaunchKernelGGL(eval_kernel<double>, dim3((unsigned)nblocks), dim3(256), 0, st, segs, nseg, grids, lines,
+                       shells, ments, wcols);
+  return hipGetLastError();
+}
+
+template <typename T, int WM, int WN, int SC>
+static hipError_t launch_contract_t(const TaskDev* tasks, const TileDev* tiles, int ntiles, double* ws,
+                                    hipStream_t st) {
+  constexpr int lds = ContractCfg<T, WM, WN, SC>::LDS_BYTES;
+  if constexpr (sizeof(T) == 8) {
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute((const void*)contract_f64<WM, WN, SC>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+      attr = true;
+    }
+    hipLaunchKernelGGL((contract_f64<WM, WN, SC>), dim3(ntiles), dim3(256), lds, st, tasks, tiles, ws);
+  } else {
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute((const void*)contract_mixed<WM, WN, SC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                lds);
+      attr = true;
+    }
+    hipLaunchKernelGGL((contract_mixed<WM, WN, SC>), dim3(ntiles), dim3(256), lds, st, tasks, tiles, ws);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_contract_any(int wm, int wn, const TaskDev* tasks, const TileDev* tiles, int ntiles,
+                                      double* ws, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  if (wm == 4 && wn == 4) return launch_contract_t<T, 4, 4, 2>(tasks, tiles, ntiles, ws, st);
+  if (wm == 2 && wn == 2) return launch_contract_t<T, 2, 2, 2>(tasks, tiles, ntiles, ws, st);
+  if (wm == 4 && wn == 2) return launch_contract_t<T, 4, 2, 2>(tasks, tiles, ntiles, ws, st);
+  if (wm == 2 && wn == 4) return launch_contract_t<T, 2, 4, 2>(tasks, tiles, ntiles, ws, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_contract_f64(int wm, int wn, const TaskDev* tasks, const TileDev* tiles, int ntiles, double* ws,
+                               hipStream_t st) {
+  return launch_contract_any<double>(wm, wn, tasks, tiles, ntiles, ws, st);
+}
+
+hipError_t launch_contract_mixed(int wm, int wn, const TaskDev* tasks, const TileDev* tiles, int ntiles, double* ws,
+                                 hipStream_t st) {
+  return launch_contract_any<float>(wm, wn, tasks, tiles, ntiles, ws, st);
+}
+
+hipError_t launch_reduce(int wm, int wn, const TaskDev* tasks, const RedDev* reds, const int32_t* items, int nitems,
+                         const double* ws, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  if (wm == 4 && wn == 4)
+    hipLaunchKernelGGL((reduce_kernel<128, 128>), dim3(nitems), dim3(256), 0, st, tasks, reds, items, ws);
+  else if (wm == 2 && wn == 2)
+    hipLaunchKernelGGL((reduce_kernel<64, 64>), dim3(nitems), dim3(256), 0, st, tasks, reds, items, ws);
+  else if (wm == 4 && wn == 2)
+    hipLaunchKernelGGL((reduce_kernel<128, 64>), dim3(nitems), dim3(256), 0, st, tasks, reds, items, ws);
+  else if (wm == 2 && wn == 4)
+    hipLaunchKernelGGL((reduce_kernel<64, 128>), dim3(nitems), dim3(256), 0, st, tasks, reds, items, ws);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_symmetrize(double* X, int n, hipStream_t st) {
+  if (n <= 1) return hipSuccess;
+  int64_t blocks = ((int64_t)n * n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)blocks), dim3(256), 0, st, X, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholesky(const double* A, double* L, int n, int* status, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = ((int64_t)n * n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(copy_lower_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, L, n, 0);
+  for (int k0 = 0; k0 < n; k0 += CB) {
+    hipLaunchKernelGGL(chol_panel, dim3(1), dim3(256), 0, st, A, L, n, k0, status);
+    const int m = n - k0 - CB;
+    if (m > 0) {
+      hipLaunchKernelGGL(chol_trsm, dim3((m + 63) / 64), dim3(256), 0, st, L, n, k0, status);
+      const int t = (m + 63) / 64;
+      hipLaunchKernelGGL(chol_update, dim3(t, t), dim3(256), 0, st, L, n, k0, status);
+    }
+  }
+  hipLaunchKernelGGL(copy_lower_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, L, n, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_points(const GridDev& G, const double* lines, const double* RA, double* xyzw, hipStream_t st) {
+  int64_t blocks = (G.npts + 255) / 256;
+  hipLaunchKernelGGL(grid_points_kernel, dim3((unsigned)blocks), dim3(256), 0, st, G, lines, RA[0], RA[1], RA[2],
+                     xyzw);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_points(int what, const ShellDev& sh, const MEntry& me, const double* c, const double* X,
+                              const double* Y, const double* Z, int64_t n, double* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(eval_points_kernel, dim3((unsigned)blocks), dim3(256), 0, st, what, sh, me, c[0], c[1], c[2], X,
+                     Y, Z, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace psint

@@ -1,0 +1,115 @@
+// Host-side planner: validation, grid construction (lines, frame, third-centre moves), routing of
+// integral blocks to grids, device array layout, evaluation segments, contraction tasks and tiles.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/psint.h"
+#include "psint_internal.h"
+
+namespace psint {
+
+// Contraction tile shape: 4 waves in a 2 x 2 arrangement, each wave WM x WN MFMA blocks of 16 x 16.
+struct TileShape {
+  int wm = 4, wn = 4;
+  int bm() const { return 32 * wm; }
+  int bn() const { return 32 * wn; }
+  int maxuv() const { return bm() + 8; }  // staged U + V columns per tile
+};
+
+struct GridHost {
+  int A, B, C;          // A < B, C = -1 for none
+  bool pair_grid;       // G(A,B|C*) or the only grid of a diatomic
+  ps_grid_spec spec;
+  GridDev dev;
+  std::vector<double> mu, nu, phi;
+};
+
+// A device array of nf columns over a grid's padded points (chunked SoA).
+struct ArrayHost {
+  int grid;
+  int nf;
+  int64_t offset;       // bytes from the pass's array region start
+  std::vector<int32_t> map;  // column -> caller index (or output selector)
+  int64_t map_off;      // int offset in the int table
+};
+
+struct SegHost {
+  SegDev dev;
+  int arr0, arr1;       // array ids
+};
+
+struct TaskHost {
+  TaskDev dev;
+  int grid;
+  int U, V, Y;          // array ids
+  int64_t pairs_off;    // int offset of the pair list
+  int out_kind;         // 0 S, 1 T, 2 V, 3 PQ, 4 abP (for offsets)
+  int64_t out_off, outm_off;  // element offsets in the internal output buffer (-1 = none)
+  int phase;
+  double pair_points;   // algorithmic work of the task (unique elements x points)
+};
+
+struct Pass {
+  int grid0, grid1;     // grids [grid0, grid1)
+  int seg0, seg1;       // segments
+  int task0, task1;     // tasks
+  int tile0, tile1;     // tiles
+  std::vector<std::vector<int>> red_by_phase;  // reduce item ids per phase
+  int64_t eval_blocks;
+  size_t array_bytes;
+  size_t ws_elems;
+};
+
+struct Plan {
+  // copied inputs
+  std::vector<ps_atom> atoms;
+  std::vector<ps_sto> basis, aux;
+  int n_bf = 0, n_aux = 0, n_atoms = 0;
+  int precision = 0;
+  TileShape tile;
+  int ksplit_override = 0;
+
+  std::vector<GridHost> grids;
+  std::vector<double> lines;         // device line buffer contents
+  std::vector<ArrayHost> arrays;
+  std::vector<ShellDev> shells;
+  std::vector<MEntry> ments;
+  std::vector<WColDev> wcols;
+  std::vector<SegHost> segs;
+  std::vector<TaskHost> tasks;
+  std::vector<TileDev> tiles;
+  std::vector<RedDev> reds;
+  std::vector<int32_t> ints;         // pair lists and column maps
+  std::vector<Pass> passes;
+
+  // internal output buffer (FP64 elements)
+  int64_t off_S = 0, off_T = 0, off_V = 0, off_PQ = 0, off_abP = 0, off_L = 0, out_elems = 0;
+
+  double pair_points = 0.0;
+  double contract_flops = 0.0;
+  double issued_flops = 0.0;
+  int64_t n_points = 0;
+  size_t max_array_bytes = 0, max_ws_bytes = 0;
+  size_t meta_bytes = 0;
+  size_t elem_size = 8;              // bytes per array element (8 FP64, 4 mixed)
+};
+
+// Validate the job; returns PS_OK or an error code with a message.
+int32_t validate_job(const ps_job* job, std::string* err);
+
+// Build the full plan.  `budget` bounds array + workspace bytes per pass.
+int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_override, size_t budget,
+                   Plan* plan, std::string* err);
+
+// Grid construction alone (used by the inspection hook).
+int32_t build_grid(const ps_atom* atoms, int n_atoms, int A, int B, int C, const ps_grid_spec& spec,
+                   GridHost* g, std::string* err);
+
+// Gauss-Legendre nodes/weights on [-1, 1].
+void gauss_legendre(int q, double* x, double* w);
+
+}  // namespace psint

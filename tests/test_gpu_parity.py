@@ -1,0 +1,200 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle, element by element.
+
+FP64 path bar: 1e-10 absolute on every element (both sides compute the same quadrature; only the
+rounding order and the evaluation formulas differ).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+import oracle as O
+from conftest import MiniJob, Spec
+from paper_2510_15204_amd import psint
+from paper_2510_15204_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = psint.Context(0)
+    yield c
+    c.close()
+
+
+def _compare(got, ref, tol, label):
+    worst = {}
+    for k in ("S", "T", "V", "PQ", "abP"):
+        d = np.max(np.abs(got[k] - ref[k])) if ref[k].size else 0.0
+        worst[k] = d
+    _say(f"{label}: max abs diff " + ", ".join(f"{k}={v:.2e}" for k, v in worst.items()))
+    for k, v in worst.items():
+        assert v <= tol, (label, k, v)
+
+
+# ---------------------------------------------------------------------------------------------
+# Grid points and weights
+# ---------------------------------------------------------------------------------------------
+
+TRI = W.triatomic_geometry()
+
+
+@pytest.mark.parametrize("A,B,C,spec", [
+    (0, 1, -1, (5, 4, 3, 4, 3, 2.3, 0.25)),
+    (0, 1, 2, (6, 5, 4, 3, 3, 2.3, 0.25)),
+    (1, 2, 0, (7, 6, 5, 2, 2, 2.3, 0.25)),
+    (0, 2, 1, (4, 4, 2, 5, 4, 2.3, 0.25)),
+])
+def test_grid_points_match_oracle(ctx, A, B, C, spec):
+    _say(f"grid points A={A} B={B} C={C} spec={spec}")
+    g = ctx.grid_points(TRI, A, B, C, Spec(*spec))
+    x, y, z, w = O.grid_points(TRI, A, B, C, spec)
+    assert g.shape[0] == x.size
+    tree = cKDTree(np.stack([x, y, z], 1))
+    d, idx = tree.query(g[:, :3])
+    assert np.max(d) < 1e-12
+    assert len(set(idx.tolist())) == x.size  # a bijection
+    assert np.max(np.abs(g[:, 3] - w[idx]) / w[idx]) < 1e-12
+
+
+# ---------------------------------------------------------------------------------------------
+# Function values: chi, -1/2 lap chi, aux potential
+# ---------------------------------------------------------------------------------------------
+
+FUNCS = [(1, 0, 0, 1.3), (2, 1, -1, 0.7), (2, 1, 1, 2.5), (3, 2, 0, 1.1), (4, 3, -2, 1.9), (5, 4, 3, 0.9),
+         (6, 5, -5, 1.5), (7, 6, 6, 2.2), (7, 6, -1, 0.6), (12, 3, 1, 1.4), (4, 0, 0, 3.5)]
+
+
+@pytest.mark.parametrize("what", ["chi", "kin", "pot"])
+def test_eval_function_matches_oracle(ctx, what):
+    rng = np.random.default_rng(11)
+    pts = rng.normal(size=(500, 3)) * rng.uniform(0.01, 6.0, size=(500, 1))
+    center = np.array([0.3, -0.2, 0.1])
+    for (n, l, m, z) in FUNCS:
+        fn = [0, n, l, m, z]
+        got = ctx.eval_function(what, fn, center, pts[:, 0] + center[0], pts[:, 1] + center[1],
+                                pts[:, 2] + center[2])
+        ref = O.eval_fn(what, fn, center, pts[:, 0] + center[0], pts[:, 1] + center[1], pts[:, 2] + center[2])
+        scale = np.max(np.abs(ref)) + 1e-300
+        err = np.max(np.abs(got - ref)) / scale
+        assert err < 1e-13, (what, n, l, m, z, err)
+
+
+# ---------------------------------------------------------------------------------------------
+# Whole jobs against the oracle
+# ---------------------------------------------------------------------------------------------
+
+def test_diatomic_small_full_parity(ctx):
+    job = W.diatomic_small()
+    _say(f"job {job.name}: n_bf={job.n_bf} n_aux={job.n_aux}")
+    got, st, rc = ctx.compute(job)
+    ref = O.compute_full(job)
+    assert rc == ref["status"] == 0
+    _compare(got, ref, TOL64, job.name)
+    assert np.max(np.abs(got["PQ_chol"] - ref["PQ_chol"])) < 1e-9
+    assert st["pair_points"] == ref["pair_points"]
+
+
+def _tri_tz(spec=(6, 5, 4, 4, 3, 2.3, 0.25)):
+    rng = W.rng_for(1)
+    Z = np.array([8.0, 1.0, 1.0])
+    basis, aux = W.build_basis(rng, Z.astype(int), "TZ", "auxTZ", n_max=4)
+    return MiniJob(TRI, Z, basis, aux, Spec(*spec))
+
+
+def test_triatomic_tz_full_parity_several_tiles(ctx):
+    """43 basis / 129 aux functions: the O x H pair block (225 rows) spans two 128-row tiles and the
+    129 aux columns two 128-column tiles (ragged tails in both)."""
+    job = _tri_tz()
+    _say(f"triatomic TZ: n_bf={len(job.basis)} n_aux={len(job.aux)}")
+    got, st, rc = ctx.compute(job)
+    ref = O.compute_full(job)
+    assert rc == ref["status"]
+    _compare(got, ref, TOL64, "triatomic TZ")
+    assert st["pair_points"] == ref["pair_points"]
+
+
+def test_four_atoms_pair_and_third_centre_grids(ctx):
+    """N = 4: grids G(A,B|C) that are not pair grids carry only V(nucleus C) and (ab|P on C)."""
+    xyz = np.array([[0.0, 0.0, 0.0], [1.9, 0.2, 0.0], [-0.4, 1.8, 0.3], [0.6, -0.5, 2.0]])
+    Z = [6.0, 1.0, 8.0, 1.0]
+    rng = np.random.default_rng(3)
+    basis = [[0, 1, 0, 0, 4.0], [0, 2, 1, 1, 1.2], [0, 3, 2, -2, 1.1], [1, 1, 0, 0, 1.3], [1, 2, 1, 0, 0.9],
+             [2, 2, 0, 0, 1.7], [2, 2, 1, -1, 1.4], [3, 1, 0, 0, 1.0]]
+    aux = [[0, 1, 0, 0, 5.0], [0, 2, 1, 0, 2.2], [1, 1, 0, 0, 2.5], [2, 3, 2, 1, 2.9], [2, 1, 0, 0, 3.3],
+           [3, 2, 1, 1, 2.0]]
+    job = MiniJob(xyz, Z, basis, aux, Spec(5, 4, 3, 3, 2))
+    got, st, rc = ctx.compute(job)
+    ref = O.compute_full(job)
+    _compare(got, ref, TOL64, "four atoms")
+    assert st["n_grids"] == 12
+    assert st["pair_points"] == ref["pair_points"]
+
+
+def test_pair_grid_overrides_and_unsorted_functions(ctx):
+    """Per-pair grid specs, functions listed out of atom order, an atom without aux functions."""
+    xyz = np.array([[0.0, 0.0, 0.0], [0.0, 1.7, 0.5], [1.5, -0.3, 0.2]])
+    basis = [[2, 1, 0, 0, 1.1], [0, 2, 1, -1, 1.3], [1, 3, 2, 2, 0.8], [0, 1, 0, 0, 3.1], [2, 2, 1, 1, 1.0],
+             [1, 1, 0, 0, 1.2]]
+    aux = [[1, 2, 1, 0, 2.4], [0, 1, 0, 0, 4.1], [1, 1, 0, 0, 2.0]]
+    pg = {(0, 2): Spec(6, 4, 3, 3, 3), (1, 2): Spec(4, 5, 4, 2, 2)}
+    job = MiniJob(xyz, [7.0, 1.0, 1.0], basis, aux, Spec(5, 5, 3, 3, 3), pg)
+    got, st, rc = ctx.compute(job)
+    ref = O.compute_full(job)
+    _compare(got, ref, TOL64, "overrides")
+    assert st["pair_points"] == ref["pair_points"]
+
+
+def test_device_outputs_equal_host_outputs(ctx):
+    job = _tri_tz((4, 4, 3, 3, 2, 2.3, 0.25))
+    host, _, _ = ctx.compute(job)
+    dev, _, _ = ctx.compute(job, device=True)
+    for k in psint.OUTPUTS:
+        assert np.array_equal(host[k], dev[k].cpu().numpy()), k
+
+
+def test_not_positive_definite_metric_reported(ctx):
+    xyz = np.array([[0.0, 0.0, 0.7], [0.0, 0.0, -0.7]])
+    job = MiniJob(xyz, [1, 1], [[0, 1, 0, 0, 1.0], [1, 1, 0, 0, 1.0]], [[0, 1, 0, 0, 2.0], [0, 1, 0, 0, 2.0]],
+                  Spec(6, 6, 4))
+    got, st, rc = ctx.compute(job)
+    assert rc == psint.PS_E_NOT_PD
+    ref = O.compute_full(job)
+    assert ref["status"] == -5
+    _compare(got, ref, TOL64, "not PD")
+
+
+@pytest.mark.parametrize("bad", ["l_ge_n", "neg_zeta", "atom_index", "coincident", "spec", "too_high_l"])
+def test_invalid_inputs_rejected(ctx, bad):
+    xyz = np.array([[0.0, 0.0, 0.7], [0.0, 0.0, -0.7]])
+    basis = [[0, 1, 0, 0, 1.0], [1, 2, 1, 0, 1.0]]
+    aux = [[0, 1, 0, 0, 2.0]]
+    spec = Spec(6, 6, 4)
+    expect = psint.PS_E_INVALID
+    if bad == "l_ge_n":
+        basis[1] = [1, 2, 2, 0, 1.0]
+    elif bad == "neg_zeta":
+        basis[0] = [0, 1, 0, 0, -1.0]
+    elif bad == "atom_index":
+        aux[0] = [5, 1, 0, 0, 2.0]
+    elif bad == "coincident":
+        xyz = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 1e-5]])
+    elif bad == "spec":
+        spec = Spec(1, 6, 4)
+    elif bad == "too_high_l":
+        basis[1] = [1, 9, 7, 0, 1.0]
+        expect = psint.PS_E_UNSUPPORTED
+    job = MiniJob(xyz, [1, 1], basis, aux, spec)
+    with pytest.raises(psint.PsError) as e:
+        ctx.compute(job)
+    assert e.value.status == expect
