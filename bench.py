@@ -36,8 +36,8 @@ def parse():
                     choices=["triatomic_qz", "triatomic_5z", "diatomic_small", "hydrocarbon9"])
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=600, help="abP elements in the oracle sample")
-    ap.add_argument("--tiling", default="0,0,0", help="wm,wn,ksplit (0 = library default)")
+    ap.add_argument("--cpu-sample", type=int, default=15000, help="abP elements in the oracle sample")
+    ap.add_argument("--tiling", default="0,0,0,0", help="wm,wn,stage_chunks,ksplit (0 = library default)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "contract_traffic.json"))
     return ap.parse_args()
 
@@ -71,9 +71,9 @@ def main():
     job = W.WORKLOADS[args.workload]()
     prec = args.precision or job.precision
     ctx = psint.Context(0)
-    wm, wn, ks = (int(x) for x in args.tiling.split(","))
-    if wm or wn or ks:
-        ctx.set_tiling(wm, wn, ks)
+    wm, wn, sc, ks = (int(x) for x in args.tiling.split(","))
+    if wm or wn or sc or ks:
+        ctx.set_tiling(wm, wn, sc, ks)
     # device outputs allocated once; the job's inputs are a few KB of host structs
     dev = torch.device("cuda:0")
     nb, na = job.n_bf, job.n_aux

@@ -152,9 +152,11 @@ int32_t ps_eval_function(ps_ctx* ctx, int32_t what, const ps_sto* fn, const doub
 int32_t ps_plan_work(ps_ctx* ctx, const ps_job* job, double* pair_points, int64_t* n_grids,
                      int64_t* n_points, size_t* device_bytes);
 
-/* Tile shape override for the contraction (0 = autotuned choice).  wm, wn: 16x16 MFMA blocks per
- * wave along the pair and column dimensions; ksplit: point splits per tile. */
-int32_t ps_set_tiling(ps_ctx* ctx, int32_t wm, int32_t wn, int32_t ksplit);
+/* Contraction tile shape for later jobs on this context (0 = the built-in default for a field).
+ * wm, wn in {2, 4}: 16x16 MFMA blocks per wave along the pair and column dimensions (a work-group
+ * tile is 32*wm pairs x 32*wn columns); stage_chunks in {1, 2}: 16-point chunks per LDS stage;
+ * ksplit: point-range splits per tile (0 = sized to fill the device).  PS_E_INVALID otherwise. */
+int32_t ps_set_tiling(ps_ctx* ctx, int32_t wm, int32_t wn, int32_t stage_chunks, int32_t ksplit);
 
 const char* ps_status_string(int32_t status);
 /* Last error text of the context (valid until the next call on it); ctx may be NULL. */

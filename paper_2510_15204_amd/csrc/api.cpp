@@ -16,10 +16,10 @@ namespace psint {
 hipError_t launch_eval(bool fp32, const SegDev* segs, int nseg, int64_t nblocks, const GridDev* grids,
                        const double* lines, const ShellDev* shells, const MEntry* ments, const WColDev* wcols,
                        hipStream_t st);
-hipError_t launch_contract_f64(int wm, int wn, const TaskDev* tasks, const TileDev* tiles, int ntiles, double* ws,
-                               hipStream_t st);
-hipError_t launch_contract_mixed(int wm, int wn, const TaskDev* tasks, const TileDev* tiles, int ntiles, double* ws,
-                                 hipStream_t st);
+hipError_t launch_contract_f64(int wm, int wn, int sc, const TaskDev* tasks, const TileDev* tiles, int ntiles,
+                               double* ws, hipStream_t st);
+hipError_t launch_contract_mixed(int wm, int wn, int sc, const TaskDev* tasks, const TileDev* tiles, int ntiles,
+                                 double* ws, hipStream_t st);
 hipError_t launch_reduce(int wm, int wn, const TaskDev* tasks, const RedDev* reds, const int32_t* items, int nitems,
                          const double* ws, hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
@@ -184,9 +184,11 @@ int32_t enqueue_job(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L) {
     }
     HIP_TRY(hipEventRecord(s.ev_contract[2 * pi], st));
     if (mixed)
-      HIP_TRY(launch_contract_mixed(p.tile.wm, p.tile.wn, tasks, tiles + ps.tile0, ps.tile1 - ps.tile0, ws, st));
+      HIP_TRY(launch_contract_mixed(p.tile.wm, p.tile.wn, p.tile.sc, tasks, tiles + ps.tile0, ps.tile1 - ps.tile0, ws,
+                                    st));
     else
-      HIP_TRY(launch_contract_f64(p.tile.wm, p.tile.wn, tasks, tiles + ps.tile0, ps.tile1 - ps.tile0, ws, st));
+      HIP_TRY(launch_contract_f64(p.tile.wm, p.tile.wn, p.tile.sc, tasks, tiles + ps.tile0, ps.tile1 - ps.tile0, ws,
+                                  st));
     HIP_TRY(hipEventRecord(s.ev_contract[2 * pi + 1], st));
     s.n_contract++;
     for (auto& ph : ps.red_by_phase) {
@@ -389,18 +391,19 @@ int32_t ps_destroy(ps_ctx* ctx) {
   return PS_OK;
 }
 
-int32_t ps_set_tiling(ps_ctx* ctx, int32_t wm, int32_t wn, int32_t ksplit) {
+int32_t ps_set_tiling(ps_ctx* ctx, int32_t wm, int32_t wn, int32_t stage_chunks, int32_t ksplit) {
   if (!ctx) return PS_E_INVALID;
-  if (wm == 0 && wn == 0) {
-    wm = 4;
-    wn = 4;
-  }
-  if (!((wm == 2 || wm == 4) && (wn == 2 || wn == 4)) || ksplit < 0) {
-    ctx->err = "tiling: wm, wn in {2, 4}, ksplit >= 0";
+  TileShape def;
+  if (wm == 0) wm = def.wm;
+  if (wn == 0) wn = def.wn;
+  if (stage_chunks == 0) stage_chunks = def.sc;
+  if (!((wm == 2 || wm == 4) && (wn == 2 || wn == 4) && (stage_chunks == 1 || stage_chunks == 2)) || ksplit < 0) {
+    ctx->err = "tiling: wm, wn in {2, 4}, stage_chunks in {1, 2}, ksplit >= 0";
     return PS_E_INVALID;
   }
   ctx->shape.wm = wm;
   ctx->shape.wn = wn;
+  ctx->shape.sc = stage_chunks;
   ctx->ksplit = ksplit;
   return PS_OK;
 }

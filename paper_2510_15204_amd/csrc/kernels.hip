@@ -319,51 +319,45 @@ __global__ __launch_bounds__(256) void eval_kernel(const SegDev* __restrict__ se
 // v_mfma_f64_16x16x4 result register r of lane l = D[4r + l/16][l%16];
 // v_mfma_f32_16x16x4f32 result register r of lane l = D[4(l/16) + r][l%16].
 // ------------------------------------------------------------------------------------------------
-template <typename T>
-struct Vec2;  // 16-byte global loads
-template <>
-struct Vec2<double> {
-  typedef double2 type;
-  static constexpr int N = 2;
-};
-template <>
-struct Vec2<float> {
-  typedef float4 type;
-  static constexpr int N = 4;
-};
-
-template <typename T, int WM, int WN, int SC>
+template <typename T, int WM, int WN, int SC_>
 struct ContractCfg {
   static constexpr int BM = 32 * WM, BN = 32 * WN;
-  static constexpr int KS = SC * KC;            // points per stage
-  static constexpr int LDK = KS + 4;            // padded LDS row
-  static constexpr int MAXUV = BM + 8;
-  static constexpr int ROWS = MAXUV + BN;
-  static constexpr int VN = Vec2<T>::N;         // values per 16-byte load
-  static constexpr int PER_ROW = KC / VN;       // loads per row per storage chunk
-  static constexpr int NPRE = (ROWS * SC * PER_ROW + 255) / 256;
-  static constexpr int LDS_BYTES = 2 * ROWS * LDK * (int)sizeof(T);
+  static constexpr int SC = SC_;                        // storage chunks per stage
+  static constexpr int KS = SC * KC;                    // points per stage
+  // padded LDS row: FP64 rows 34 doubles (68 words: 16 consecutive rows at the same k fall in distinct
+  // banks within a half-wave), FP32 rows 36 floats (same property)
+  static constexpr int LDK = KS + (sizeof(T) == 8 ? 2 : 4);
+  static constexpr int SLOTS = LDK * (int)sizeof(T) / 16;       // 16-byte slots per row
+  static constexpr int DSLOTS = KS * (int)sizeof(T) / 16;       // slots holding data
+  static constexpr int VN = 16 / (int)sizeof(T);                // values per slot
+  static constexpr int OVER = (63 + SLOTS - 1) / SLOTS;         // rows a 64-slot copy can overshoot
+  static constexpr int MAXUV = BM + 4 + OVER;           // the host keeps nu + nv <= BM + 4
+  static constexpr int ROWS = MAXUV + BN + OVER;
+  static constexpr int BUF = ROWS * LDK;                // elements per stage buffer
+  static constexpr int LDS_BYTES = 2 * BUF * (int)sizeof(T);
 };
 
-template <typename T, int WM, int WN, int SC>
-__device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, const TileDev& t, T* __restrict__ lds,
-                                              double* __restrict__ ws) {
-  typedef ContractCfg<T, WM, WN, SC> Cf;
-  constexpr int BM = Cf::BM, BN = Cf::BN, LDK = Cf::LDK, MAXUV = Cf::MAXUV, ROWS = Cf::ROWS;
-  constexpr int VN = Cf::VN, PER_ROW = Cf::PER_ROW, NPRE = Cf::NPRE, KS = Cf::KS;
-  typedef typename Vec2<T>::type V2;
+// One work-group's tile: C[(u,v)][y] partial over chunks [kc0, kc0 + nkc) (nkc a multiple of SC).
+//
+// Staging uses direct global->LDS copies (global_load_lds_dwordx4): one wave instruction fills 64
+// consecutive 16-byte LDS slots (lane i -> slot base + i) of a region of contiguous rows, the U+V
+// rows [0, nu+nv) or the Y rows [MAXUV, MAXUV+np).  Each thread's source offset for every copy it
+// issues is computed once per tile; per stage only the chunk base moves.  The copies of stage s+1
+// are spread between the MFMA steps of stage s so their address work hides under the matrix pipe.
+template <typename T, int WM, int WN, int SC_>
+__device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, const TileDev& t,
+                                              __attribute__((address_space(3))) T* lds, double* __restrict__ ws) {
+  typedef ContractCfg<T, WM, WN, SC_> Cf;
+  constexpr int BN = Cf::BN, LDK = Cf::LDK, MAXUV = Cf::MAXUV, KS = Cf::KS, SC = Cf::SC, BUF = Cf::BUF;
+  constexpr int SLOTS = Cf::SLOTS, DSLOTS = Cf::DSLOTS, VN = Cf::VN;
+  constexpr int NCUV = (MAXUV * SLOTS + 255) / 256;  // copies per thread per stage, U+V region (max)
+  constexpr int NCY = (BN * SLOTS + 255) / 256;      // Y region (max)
+  constexpr int KSTEPS = KS / 4;
   constexpr bool F64 = sizeof(T) == 8;
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform, lets tests below be scalar
   const int wm = wave >> 1, wn = wave & 1;
   const int kl = lane >> 4;
-  T* buf[2] = {lds, lds + ROWS * LDK};
-
-  // Y rows past np stay zero in both buffers
-  for (int e = tid; e < (BN - t.np) * LDK; e += 256) {
-    buf[0][(MAXUV + t.np) * LDK + e] = (T)0;
-    buf[1][(MAXUV + t.np) * LDK + e] = (T)0;
-  }
 
   int offU[WM], offV[WM];
   bool valid[WM];
@@ -380,48 +374,66 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
     offV[mb] = (t.nu + v - t.vlo) * LDK + kl;
   }
   int offY[WN];
+  bool ycol[WN];
 #pragma unroll
-  for (int nb = 0; nb < WN; ++nb) offY[nb] = (MAXUV + wn * 16 * WN + nb * 16 + (lane & 15)) * LDK + kl;
+  for (int nb = 0; nb < WN; ++nb) {
+    const int col = wn * 16 * WN + nb * 16 + (lane & 15);
+    ycol[nb] = col < t.np;
+    offY[nb] = (MAXUV + col) * LDK + kl;
+  }
 
-  // staging map: a stage is SC chunks; chunk j's three runs (U, V, Y columns) concatenated
   const T* __restrict__ Ub = (const T*)Tk.U + (int64_t)t.ulo * KC;
   const T* __restrict__ Vb = (const T*)Tk.V + (int64_t)t.vlo * KC;
   const T* __restrict__ Yb = (const T*)Tk.Y + (int64_t)(Tk.y0 + t.p0) * KC;
   const int64_t sU = (int64_t)Tk.nfU * KC, sV = (int64_t)Tk.nfV * KC, sY = (int64_t)Tk.nfY * KC;
-  const int nUe = t.nu * PER_ROW, nUVe = nUe + t.nv * PER_ROW, tote = nUVe + t.np * PER_ROW;
-  const int64_t c_end = t.kc0 + t.nkc;
-  const int nstage = (int)((t.nkc + SC - 1) / SC);
+  const int nstage = (int)(t.nkc / SC);
+  const int nslot_uv = (t.nu + t.nv) * SLOTS, nslot_y = t.np * SLOTS;
 
-  V2 pre[NPRE];
-  auto load_stage = [&](int s) {
+  // per-thread copy descriptors: element offset from the stage's chunk base; bit 30 marks a V source
+  int cuv[NCUV], cy[NCY];
 #pragma unroll
-    for (int i = 0; i < NPRE; ++i) {
-      const int e = tid + 256 * i;
-      const int j = e / tote, e2 = e - j * tote;
-      const int64_t c = t.kc0 + (int64_t)s * SC + j;
-      if (j < SC && c < c_end) {
-        const V2* p;
-        if (e2 < nUe) p = (const V2*)(Ub + c * sU) + e2;
-        else if (e2 < nUVe) p = (const V2*)(Vb + c * sV) + (e2 - nUe);
-        else p = (const V2*)(Yb + c * sY) + (e2 - nUVe);
-        pre[i] = *p;
-      } else {
-        pre[i] = V2{};
-      }
+  for (int i = 0; i < NCUV; ++i) {
+    const int slot = wave * 64 + 256 * i + lane;
+    const int row = slot / SLOTS, q = slot - row * SLOTS;
+    int d = 0;
+    if (slot < nslot_uv && q < DSLOTS) {
+      const int e = q * VN, j = e / KC, k = e - j * KC;
+      d = row < t.nu ? (int)(j * sU) + row * KC + k : ((int)(j * sV) + (row - t.nu) * KC + k) | (1 << 30);
     }
-  };
-  auto store_part = [&](T* dst, int i) {
-    const int e = tid + 256 * i;
-    const int j = e / tote, e2 = e - j * tote;
-    if (j < SC) {
-      int row, kq;
-      if (e2 < nUe) { row = e2 / PER_ROW; kq = e2 - row * PER_ROW; }
-      else if (e2 < nUVe) { row = t.nu + (e2 - nUe) / PER_ROW; kq = (e2 - nUe) % PER_ROW; }
-      else { row = MAXUV + (e2 - nUVe) / PER_ROW; kq = (e2 - nUVe) % PER_ROW; }
-      T* d = dst + row * LDK + j * KC + kq * VN;
-      const T* v = (const T*)&pre[i];
+    cuv[i] = d;
+  }
 #pragma unroll
-      for (int q = 0; q < VN; ++q) d[q] = v[q];
+  for (int i = 0; i < NCY; ++i) {
+    const int slot = wave * 64 + 256 * i + lane;
+    const int row = slot / SLOTS, q = slot - row * SLOTS;
+    int d = 0;
+    if (slot < nslot_y && q < DSLOTS) {
+      const int e = q * VN, j = e / KC, k = e - j * KC;
+      d = (int)(j * sY) + row * KC + k;
+    }
+    cy[i] = d;
+  }
+  // copy i of the U+V region (i < NCUV) or Y region (NCUV <= i < NCUV + NCY) of stage s
+  auto copy = [&](int s, int i) {
+    __attribute__((address_space(3))) T* b = lds + (s & 1) * BUF;
+    const int64_t c = t.kc0 + (int64_t)s * SC;
+    if (i < NCUV) {
+      const int base = wave * 64 + 256 * i;
+      if (base < nslot_uv) {
+        const int d = cuv[i];
+        const T* src = (d & (1 << 30)) ? Vb + c * sV + (d & ~(1 << 30)) : Ub + c * sU + d;
+        __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)(b + base * VN),
+                                         16, 0, 0);
+      }
+    } else {
+      const int ii = i - NCUV;
+      const int base = wave * 64 + 256 * ii;
+      if (base < nslot_y) {
+        const T* src = Yb + c * sY + cy[ii];
+        __builtin_amdgcn_global_load_lds((const void*)src,
+                                         (__attribute__((address_space(3))) void*)(b + MAXUV * LDK + base * VN), 16,
+                                         0, 0);
+      }
     }
   };
 
@@ -432,17 +444,16 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
 #pragma unroll
     for (int nb = 0; nb < WN; ++nb) acc[mb][nb] = (d4_t){0.0, 0.0, 0.0, 0.0};
 
-  load_stage(0);
+  if (nstage > 0) {
 #pragma unroll
-  for (int i = 0; i < NPRE; ++i) store_part(buf[0], i);
-  if (nstage > 1) load_stage(1);
+    for (int i = 0; i < NCUV + NCY; ++i) copy(0, i);
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-
-  constexpr int KSTEPS = KS / 4;
-  for (int s = 0; s < nstage; ++s) {
-    const T* cur = buf[s & 1];
-    T* nxt = buf[(s + 1) & 1];
+  // one stage: MFMAs on the current buffer, copies of the next stage into the other
+  auto run_stage = [&](int s) {
     const bool more = s + 1 < nstage;
+    const __attribute__((address_space(3))) T* cur = lds + (s & 1) * BUF;
     Acc a32[WM][WN];
     if constexpr (!F64) {
 #pragma unroll
@@ -450,16 +461,27 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
 #pragma unroll
         for (int nb = 0; nb < WN; ++nb) a32[mb][nb] = Acc{};
     }
-#pragma unroll
-    for (int kk = 0; kk < KSTEPS; ++kk) {
-      T av[WM], bv[WN];
+    // operands of step kk+1 are read from LDS while the MFMAs of step kk run
+    T uA[2][WM], vA[2][WM], yB[2][WN];
+    auto fetch = [&](int kk, int slot) {
 #pragma unroll
       for (int mb = 0; mb < WM; ++mb) {
-        const T p = cur[offU[mb] + 4 * kk] * cur[offV[mb] + 4 * kk];
-        av[mb] = valid[mb] ? p : (T)0;
+        uA[slot][mb] = cur[offU[mb] + 4 * kk];
+        vA[slot][mb] = cur[offV[mb] + 4 * kk];
       }
 #pragma unroll
-      for (int nb = 0; nb < WN; ++nb) bv[nb] = cur[offY[nb] + 4 * kk];
+      for (int nb = 0; nb < WN; ++nb) yB[slot][nb] = cur[offY[nb] + 4 * kk];
+    };
+    fetch(0, 0);
+#pragma unroll
+    for (int kk = 0; kk < KSTEPS; ++kk) {
+      const int sl = kk & 1;
+      if (kk + 1 < KSTEPS) fetch(kk + 1, sl ^ 1);
+      T av[WM], bv[WN];
+#pragma unroll
+      for (int mb = 0; mb < WM; ++mb) av[mb] = valid[mb] ? uA[sl][mb] * vA[sl][mb] : (T)0;
+#pragma unroll
+      for (int nb = 0; nb < WN; ++nb) bv[nb] = ycol[nb] ? yB[sl][nb] : (T)0;
 #pragma unroll
       for (int mb = 0; mb < WM; ++mb)
 #pragma unroll
@@ -469,11 +491,11 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
           else
             a32[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb], bv[nb], a32[mb][nb], 0, 0, 0);
         }
-      // spread the next stage's LDS writes over the MFMA steps
+      // the next stage's copies, spread over the steps (into the other buffer)
       if (more) {
 #pragma unroll
-        for (int i = 0; i < NPRE; ++i)
-          if (i % KSTEPS == kk) store_part(nxt, i);
+        for (int i = 0; i < NCUV + NCY; ++i)
+          if (i % KSTEPS == kk) copy(s + 1, i);
       }
     }
     if constexpr (!F64) {
@@ -485,9 +507,12 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc[mb][nb][r] += (double)a32[mb][nb][r];
     }
-    if (s + 2 < nstage) load_stage(s + 2);
+    // keep this stage's MFMAs ahead of the wait for the next stage's copies
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-  }
+  };
+  for (int s = 0; s < nstage; ++s) run_stage(s);
   double* __restrict__ wt = ws + t.ws;
 #pragma unroll
   for (int mb = 0; mb < WM; ++mb)
@@ -505,18 +530,18 @@ template <int WM, int WN, int SC>
 __global__ __launch_bounds__(256, 1) void contract_f64(const TaskDev* __restrict__ tasks,
                                                        const TileDev* __restrict__ tiles,
                                                        double* __restrict__ ws) {
-  extern __shared__ __attribute__((aligned(16))) char smem[];
+  extern __shared__ __attribute__((aligned(16))) double smem_d[];
   const TileDev t = tiles[blockIdx.x];
-  contract_body<double, WM, WN, SC>(tasks[t.task], t, (double*)smem, ws);
+  contract_body<double, WM, WN, SC>(tasks[t.task], t, (__attribute__((address_space(3))) double*)smem_d, ws);
 }
 
 template <int WM, int WN, int SC>
 __global__ __launch_bounds__(256, 1) void contract_mixed(const TaskDev* __restrict__ tasks,
                                                          const TileDev* __restrict__ tiles,
                                                          double* __restrict__ ws) {
-  extern __shared__ __attribute__((aligned(16))) char smem[];
+  extern __shared__ __attribute__((aligned(16))) float smem_f[];
   const TileDev t = tiles[blockIdx.x];
-  contract_body<float, WM, WN, SC>(tasks[t.task], t, (float*)smem, ws);
+  contract_body<float, WM, WN, SC>(tasks[t.task], t, (__attribute__((address_space(3))) float*)smem_f, ws);
 }
 
 // Sum the splits of each reduction item in order and scatter into the FP64 output buffer.
@@ -786,44 +811,41 @@ template <typename T, int WM, int WN, int SC>
 static hipError_t launch_contract_t(const TaskDev* tasks, const TileDev* tiles, int ntiles, double* ws,
                                     hipStream_t st) {
   constexpr int lds = ContractCfg<T, WM, WN, SC>::LDS_BYTES;
-  if constexpr (sizeof(T) == 8) {
-    static bool attr = false;
-    if (!attr) {
-      (void)hipFuncSetAttribute((const void*)contract_f64<WM, WN, SC>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-      attr = true;
-    }
-    hipLaunchKernelGGL((contract_f64<WM, WN, SC>), dim3(ntiles), dim3(256), lds, st, tasks, tiles, ws);
-  } else {
-    static bool attr = false;
-    if (!attr) {
-      (void)hipFuncSetAttribute((const void*)contract_mixed<WM, WN, SC>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                lds);
-      attr = true;
-    }
-    hipLaunchKernelGGL((contract_mixed<WM, WN, SC>), dim3(ntiles), dim3(256), lds, st, tasks, tiles, ws);
+  static_assert(lds <= 160 * 1024, "LDS budget");
+  const void* fn = sizeof(T) == 8 ? (const void*)contract_f64<WM, WN, SC> : (const void*)contract_mixed<WM, WN, SC>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    attr = true;
   }
+  if constexpr (sizeof(T) == 8)
+    hipLaunchKernelGGL((contract_f64<WM, WN, SC>), dim3(ntiles), dim3(256), lds, st, tasks, tiles, ws);
+  else
+    hipLaunchKernelGGL((contract_mixed<WM, WN, SC>), dim3(ntiles), dim3(256), lds, st, tasks, tiles, ws);
   return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t launch_contract_any(int wm, int wn, const TaskDev* tasks, const TileDev* tiles, int ntiles,
+static hipError_t launch_contract_any(int wm, int wn, int sc, const TaskDev* tasks, const TileDev* tiles, int ntiles,
                                       double* ws, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  if (wm == 4 && wn == 4) return launch_contract_t<T, 4, 4, 2>(tasks, tiles, ntiles, ws, st);
-  if (wm == 2 && wn == 2) return launch_contract_t<T, 2, 2, 2>(tasks, tiles, ntiles, ws, st);
-  if (wm == 4 && wn == 2) return launch_contract_t<T, 4, 2, 2>(tasks, tiles, ntiles, ws, st);
-  if (wm == 2 && wn == 4) return launch_contract_t<T, 2, 4, 2>(tasks, tiles, ntiles, ws, st);
+#define PS_SHAPE(a, b, c) \
+  if (wm == a && wn == b && sc == c) return launch_contract_t<T, a, b, c>(tasks, tiles, ntiles, ws, st);
+  PS_SHAPE(4, 4, 1) PS_SHAPE(4, 4, 2) PS_SHAPE(2, 2, 1) PS_SHAPE(2, 2, 2)
+  PS_SHAPE(4, 2, 1) PS_SHAPE(4, 2, 2) PS_SHAPE(2, 4, 1) PS_SHAPE(2, 4, 2)
+#undef PS_SHAPE
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_contract_f64(int wm, int wn, const TaskDev* tasks, const TileDev* tiles, int ntiles, double* ws,
-                               hipStream_t st) {
-  return launch_contract_any<double>(wm, wn, tasks, tiles, ntiles, ws, st);
+hipError_t launch_contract_f64(int wm, int wn, int sc, const TaskDev* tasks, const TileDev* tiles, int ntiles,
+                               double* ws, hipStream_t st) {
+  return launch_contract_any<double>(wm, wn, sc, tasks, tiles, ntiles, ws, st);
 }
 
-hipError_t launch_contract_mixed(int wm, int wn, const TaskDev* tasks, const TileDev* tiles, int ntiles, double* ws,
-                                 hipStream_t st) {
-  return launch_contract_any<float>(wm, wn, tasks, tiles, ntiles, ws, st);
+hipError_t launch_contract_mixed(int wm, int wn, int sc, const TaskDev* tasks, const TileDev* tiles, int ntiles,
+                                 double* ws, hipStream_t st) {
+  return launch_contract_any<float>(wm, wn, sc, tasks, tiles, ntiles, ws, st);
 }
 
 hipError_t launch_reduce(int wm, int wn, const TaskDev* tasks, const RedDev* reds, const int32_t* items, int nitems,

@@ -309,6 +309,60 @@ int32_t build_grid(const ps_atom* atoms, int n_atoms, int A, int B, int C, const
   return PS_OK;
 }
 
+// Launch order of a pass's tiles.  Work-groups are dispatched round-robin over the 8 XCDs
+// (blockIdx mod 8), each with its own L2.  Tiles that stage the same Y columns over the same point
+// range (same task, column tile and split; different pair-row tiles) form a group; a group is placed
+// on one XCD's queue and its members get consecutive slots there, so they run together and share
+// the Y columns in that XCD's L2.  Groups go to the least-loaded queue; the queues are then
+// interleaved into blockIdx order.
+static void xcd_order(std::vector<TileDev>& tiles, int t0, int t1) {
+  constexpr int NX = 8;
+  if (t1 - t0 <= NX) return;
+  std::map<std::tuple<int, int, int64_t>, std::vector<int>> groups;
+  std::vector<std::tuple<int, int, int64_t>> order_keys;
+  for (int i = t0; i < t1; ++i) {
+    const TileDev& t = tiles[i];
+    auto key = std::make_tuple(t.task, t.p0, t.kc0);
+    auto it = groups.find(key);
+    if (it == groups.end()) {
+      order_keys.push_back(key);
+      groups[key] = {i};
+    } else {
+      it->second.push_back(i);
+    }
+  }
+  std::vector<std::vector<int>> q(NX);
+  std::vector<double> load(NX, 0.0);
+  for (auto& key : order_keys) {
+    auto& g = groups[key];
+    int best = 0;
+    for (int x = 1; x < NX; ++x)
+      if (load[x] < load[best]) best = x;
+    for (int i : g) {
+      q[best].push_back(i);
+      load[best] += (double)tiles[i].nkc;
+    }
+  }
+  std::vector<TileDev> out;
+  out.reserve(t1 - t0);
+  std::vector<size_t> pos(NX, 0);
+  while ((int)out.size() < t1 - t0) {
+    for (int x = 0; x < NX; ++x) {
+      if (pos[x] < q[x].size()) {
+        out.push_back(tiles[q[x][pos[x]++]]);
+      } else {
+        // this queue ran dry: take from the longest remaining one to keep blockIdx dense
+        int lx = -1;
+        size_t rem = 0;
+        for (int y = 0; y < NX; ++y)
+          if (q[y].size() - pos[y] > rem) { rem = q[y].size() - pos[y]; lx = y; }
+        if (lx >= 0) out.push_back(tiles[q[lx][pos[lx]++]]);
+      }
+    }
+  }
+  std::copy(out.begin(), out.end(), tiles.begin() + t0);
+}
+
 int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_override, size_t budget,
                    Plan* P, std::string* err) {
   int32_t rc = validate_job(job, err);
@@ -899,7 +953,8 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
           ns = p.ksplit_override;
         else
           ns = (int64_t)std::llround(target * it.cost / std::max(total_cost, 1.0));
-        ns = std::max<int64_t>(1, std::min<int64_t>(ns, std::max<int64_t>(1, nch / 16)));
+        const int64_t nst = nch / TileShape::SC_MAX;  // whole stages (nch is a multiple of 16)
+        ns = std::max<int64_t>(1, std::min<int64_t>(ns, std::max<int64_t>(1, nst / 8)));
         RedDev rd;
         rd.task = it.task;
         rd.row0 = it.row0;
@@ -920,8 +975,8 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
           td.nv = it.nv;
           td.p0 = it.p0;
           td.np = it.np;
-          td.kc0 = nch * s / ns;
-          td.nkc = nch * (s + 1) / ns - td.kc0;
+          td.kc0 = TileShape::SC_MAX * (nst * s / ns);
+          td.nkc = TileShape::SC_MAX * (nst * (s + 1) / ns) - td.kc0;
           td.ws = ws + s * (int64_t)BM * BN;
           p.issued_flops += 2.0 * BM * BN * (double)td.nkc * KC;
           p.tiles.push_back(td);
@@ -934,6 +989,7 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       }
       ps.tile1 = (int)p.tiles.size();
       ps.ws_elems = (size_t)ws;
+      xcd_order(p.tiles, ps.tile0, ps.tile1);
       p.max_ws_bytes = std::max(p.max_ws_bytes, (size_t)ws * 8);
     }
   }

@@ -15,9 +15,11 @@ namespace psint {
 // Contraction tile shape: 4 waves in a 2 x 2 arrangement, each wave WM x WN MFMA blocks of 16 x 16.
 struct TileShape {
   int wm = 4, wn = 4;
+  int sc = 1;                             // storage chunks (16 points each) per contraction stage
   int bm() const { return 32 * wm; }
   int bn() const { return 32 * wn; }
-  int maxuv() const { return bm() + 8; }  // staged U + V columns per tile
+  int maxuv() const { return bm() + 4; }  // staged U + V columns per tile
+  static constexpr int SC_MAX = 2;        // tiles start and end on multiples of this many chunks
 };
 
 struct GridHost {

@@ -96,7 +96,7 @@ def lib():
         L.ps_eval_function.argtypes = [vp, C.c_int32, C.POINTER(Sto), _dp, C.c_int64, _dp, _dp, _dp, _dp]
         L.ps_plan_work.argtypes = [vp, C.POINTER(Job), _dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_size_t)]
-        L.ps_set_tiling.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+        L.ps_set_tiling.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.ps_status_string.argtypes = [C.c_int32]
         L.ps_status_string.restype = C.c_char_p
         L.ps_last_error.argtypes = [vp]
@@ -209,8 +209,8 @@ class Context:
             raise PsError(rc, (msg or b"").decode() or lib().ps_status_string(rc).decode())
         return rc
 
-    def set_tiling(self, wm=0, wn=0, ksplit=0):
-        self._check(lib().ps_set_tiling(self.h, wm, wn, ksplit))
+    def set_tiling(self, wm=0, wn=0, stage_chunks=0, ksplit=0):
+        self._check(lib().ps_set_tiling(self.h, wm, wn, stage_chunks, ksplit))
 
     def plan_work(self, job, precision=None):
         ref = _JobRef(job, precision)
