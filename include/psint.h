@@ -110,6 +110,7 @@ typedef struct {
   double contract_ms;    /* time inside the contraction kernels, HIP events                      */
   double contract_flops; /* algorithmic FLOPs of the contraction kernels (2 per pair-point)      */
   double issued_flops;   /* FLOPs the contraction tiles issue, padding included                   */
+  int64_t n_passes;      /* grid batches run one after another to fit the device-memory budget   */
 } ps_job_stats;
 
 typedef struct ps_ctx ps_ctx;

@@ -289,6 +289,7 @@ int32_t finish_stats(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, ps_jo
     st->pair_points = p.pair_points;
     st->contract_flops = p.contract_flops;
     st->issued_flops = p.issued_flops;
+    st->n_passes = (int64_t)p.passes.size();
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, s.ev_start, s.ev_kernels_done) == hipSuccess) st->device_ms = ms;
     double cms = 0.0;

@@ -820,8 +820,11 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
   const size_t es = p.elem_size;
   std::vector<size_t> grid_bytes(p.grids.size(), 0);
   for (auto& a : p.arrays) grid_bytes[a.grid] += (size_t)a.nf * p.grids[a.grid].dev.npad * es;
-  const size_t ws_cap = (size_t)std::max<int64_t>(8192, 0) * BM * BN * 8;
-  size_t arr_budget = budget > ws_cap ? budget - ws_cap : 0;
+  // reserve room for the partial tiles of a pass (about 2048 work-groups plus one per tile item) and
+  // the output buffer; the rest holds the arrays of the pass's grids
+  const size_t out_bytes = (size_t)p.out_elems * 8;
+  const size_t ws_cap = std::min<size_t>((size_t)4096 * BM * BN * 8, budget / 4);
+  size_t arr_budget = budget > ws_cap + out_bytes ? budget - ws_cap - out_bytes : 0;
   {
     int g0 = 0;
     while (g0 < (int)p.grids.size()) {
@@ -940,8 +943,10 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
           }
         }
       }
-      // K splits: aim for about 8 work-groups per CU in total over 256 CUs
-      const double target = 2048.0;
+      // K splits: aim for about 8 work-groups per CU in total over 256 CUs, within the workspace
+      // reservation (one BM x BN FP64 partial tile per work-group)
+      const double ws_tiles = (double)ws_cap / ((double)BM * BN * 8);
+      const double target = std::max((double)items.size(), std::min(2048.0, ws_tiles));
       int64_t ws = 0;
       ps.tile0 = (int)p.tiles.size();
       ps.red_by_phase.clear();
