@@ -33,12 +33,19 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="triatomic_qz",
-                    choices=["triatomic_qz", "triatomic_5z", "diatomic_small", "hydrocarbon9"])
+                    choices=["triatomic_qz", "triatomic_5z", "diatomic_small", "hydrocarbon9", "serving_stream"])
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose the contraction tiling with ps_autotune before the timed steps")
+    ap.add_argument("--requests", type=int, default=40, help="serving_stream: measured requests")
+    ap.add_argument("--warmup-requests", type=int, default=3, help="serving_stream: untimed requests")
+    ap.add_argument("--rate", type=float, default=50.0, help="serving_stream: Poisson arrival rate, 1/s")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=15000, help="abP elements in the oracle sample")
     ap.add_argument("--tiling", default="0,0,0,0", help="wm,wn,stage_chunks,ksplit (0 = library default)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "contract_traffic.json"))
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -65,15 +72,33 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        src = torch.ones(n // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}), flush=True)
+        return
     from paper_2510_15204_amd import psint
     from paper_2510_15204_amd import workloads as W
 
+    if args.workload == "serving_stream":
+        return serve_bench(args, torch, psint, W)
     job = W.WORKLOADS[args.workload]()
     prec = args.precision or job.precision
     ctx = psint.Context(0)
     wm, wn, sc, ks = (int(x) for x in args.tiling.split(","))
     if wm or wn or sc or ks:
         ctx.set_tiling(wm, wn, sc, ks)
+    tuning = None
+    if args.autotune:
+        best, table = ctx.autotune(job, precision=prec, reps=1)
+        tuning = {"chosen": [best["wm"], best["wn"], best["stage_chunks"], best["ksplit"]],
+                  "device_ms": {f"{t['wm']}x{t['wn']}x{t['stage_chunks']}": round(t["device_ms"], 3)
+                                for t in table}}
+        print(f"[bench] autotune: {tuning}", flush=True)
     # device outputs allocated once; the job's inputs are a few KB of host structs
     dev = torch.device("cuda:0")
     nb, na = job.n_bf, job.n_aux
@@ -122,9 +147,12 @@ def main():
            "data": "synthetic",
            "config": {"workload": job.name, "atoms": job.n_atoms, "n_bf": nb, "n_aux": na,
                       "grids": int(stats["n_grids"]), "points": int(stats["n_points"]),
-                      "pair_points_per_step": pp, "precision": prec},
+                      "pair_points_per_step": pp, "precision": prec, "passes": int(stats["n_passes"]),
+                      "tiling": tuning["chosen"] if tuning else args.tiling},
            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
            "roofline": roofline}
+    if tuning:
+        out["autotune"] = tuning
     if not args.no_cpu_baseline:
         import oracle as O
         rng = np.random.default_rng(15204)
@@ -145,6 +173,70 @@ def main():
                                          f"{args.cpu_sample} of (ab|P)) of the same job, "
                                          f"{wpp:.3e} pair-points in {cdt:.1f} s"}
         out["error_vs_fp64_oracle"] = err
+    print(json.dumps(out), flush=True)
+
+
+def serve_bench(args, torch, psint, W):
+    """Continuous-batching run of the Poisson serving stream: requests are submitted at their arrival
+    times from this thread while a second thread waits for them in order; latency = completion -
+    arrival.  The first requests run alone (untimed) to warm up."""
+    import threading
+    n_warm, n_meas = args.warmup_requests, args.requests
+    reqs = W.serving_stream(n_requests=n_warm + n_meas, rate_per_s=args.rate)
+    prec = args.precision or "mixed"
+    ctx = psint.Context(0)
+    for i in range(n_warm):
+        ctx.compute(reqs[i][1], outputs=("S", "T", "V", "PQ", "abP"), precision=prec, device=True)
+        print(f"[bench] warmup request {i + 1}/{n_warm} done", flush=True)
+    torch.cuda.synchronize()
+    meas = reqs[n_warm:]
+    t_first = meas[0][0]
+    handles = [None] * n_meas
+    done = [None] * n_meas
+    ready = threading.Semaphore(0)
+
+    def waiter():
+        for i in range(n_meas):
+            ready.acquire()
+            _, st, rc = ctx.wait(handles[i])
+            done[i] = (time.perf_counter(), st, rc)
+            handles[i] = None  # release the device outputs
+            if (i + 1) % 10 == 0:
+                print(f"[bench] {i + 1}/{n_meas} requests complete", flush=True)
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    arrivals = []
+    for i, (ta, job) in enumerate(meas):
+        due = t0 + (ta - t_first)
+        now = time.perf_counter()
+        if due > now:
+            time.sleep(due - now)
+        arrivals.append(due)
+        handles[i] = ctx.submit(job, outputs=("S", "T", "V", "PQ", "abP"), precision=prec, device=True)
+        ready.release()
+    th.join()
+    torch.cuda.synchronize()
+    t_end = max(d[0] for d in done)
+    makespan = t_end - t0
+    lat = np.array([(d[0] - a) * 1e3 for d, a in zip(done, arrivals)])
+    pp = sum(d[1]["pair_points"] for d in done)
+    atoms = [job.n_atoms for _, job in meas]
+    out = {"metric": "S/T/V/(ab|P) quadrature pair·points/s at stated error vs FP64; p99 job latency",
+           "value": pp / makespan, "unit": "pair·points/s", "n_gpus": 1, "steps": n_meas,
+           "warmup": n_warm, "ms_per_step": makespan * 1e3 / n_meas, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == "fp64" else "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": "serving_stream", "requests": n_meas, "rate_per_s": args.rate,
+                      "atoms_min_max": [min(atoms), max(atoms)], "precision": prec,
+                      "pair_points_total": pp},
+           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                          "max": float(lat.max())},
+           "serving": {"makespan_s": makespan, "capacity_requests_per_s": n_meas / makespan,
+                       "offered_load": args.rate * makespan / n_meas,
+                       "mean_queue_ms": float(np.mean([d[1]["queue_ms"] for d in done])),
+                       "not_pd": int(sum(d[2] == psint.PS_E_NOT_PD for d in done))}}
     print(json.dumps(out), flush=True)
 
 

@@ -159,6 +159,22 @@ int32_t ps_plan_work(ps_ctx* ctx, const ps_job* job, double* pair_points, int64_
  * ksplit: point-range splits per tile (0 = sized to fill the device).  PS_E_INVALID otherwise. */
 int32_t ps_set_tiling(ps_ctx* ctx, int32_t wm, int32_t wn, int32_t stage_chunks, int32_t ksplit);
 
+/* ---- tile-shape autotuner ------------------------------------------------------------------- */
+typedef struct {
+  int32_t wm, wn, stage_chunks, ksplit; /* as ps_set_tiling                                         */
+  double device_ms;                     /* best device time of the job (first -> last kernel), ms    */
+  double contract_ms;                   /* contraction kernels within that run, ms                    */
+} ps_tuning;
+
+/* Time the job's device work `reps` times (reps >= 1) under each candidate tiling (wm, wn in {2, 4},
+ * stage_chunks in {1, 2}, ksplit 0), keep the fastest on the context as ps_set_tiling would, and
+ * return it in *best.  The job's output buffers are not written.  `table` (may be NULL when
+ * max_table is 0) receives up to max_table timed candidates in trial order, *n_table (may be NULL)
+ * their number.  A candidate whose workspace exceeds the budget is skipped; PS_E_NOMEM if all are.
+ * Errors in the job itself return as from ps_compute and leave the tiling unchanged. */
+int32_t ps_autotune(ps_ctx* ctx, const ps_job* job, int32_t reps, ps_tuning* best, ps_tuning* table,
+                    int32_t max_table, int32_t* n_table);
+
 const char* ps_status_string(int32_t status);
 /* Last error text of the context (valid until the next call on it); ctx may be NULL. */
 const char* ps_last_error(ps_ctx* ctx);

@@ -6,21 +6,21 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpsint.so")
-SOURCES = ["kernels.hip", "plan.cpp", "api.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "plan.cpp", "api.cpp", "serve.cpp", "autotune.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          # no packed FP32 instructions (see the packed-math note in the design document)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-Wno-unused-function"]
 
 
-def build(verbose=False, jobs=4):
+def build(verbose=False, jobs=4, extra_flags=(), lib=LIB):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     procs, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        cmd = [hipcc] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc] + FLAGS + list(extra_flags) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if not src.endswith(".hip"):
             cmd.insert(1, "-xhip")
         if verbose:
@@ -30,12 +30,12 @@ def build(verbose=False, jobs=4):
         if len(procs) >= jobs:
             _drain(procs)
     _drain(procs)
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs + ["-lpthread"]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", lib + ".tmp"] + objs + ["-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 def _drain(procs):

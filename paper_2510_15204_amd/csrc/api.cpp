@@ -20,7 +20,7 @@ hipError_t launch_contract_f64(int wm, int wn, int sc, const TaskDev* tasks, con
                                double* ws, hipStream_t st);
 hipError_t launch_contract_mixed(int wm, int wn, int sc, const TaskDev* tasks, const TileDev* tiles, int ntiles,
                                  double* ws, hipStream_t st);
-hipError_t launch_reduce(int wm, int wn, const TaskDev* tasks, const RedDev* reds, const int32_t* items, int nitems,
+hipError_t launch_reduce(const TaskDev* tasks, const RedDev* reds, const int32_t* items, int nitems,
                          const double* ws, hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_symmetrize(double* X, int n, hipStream_t st);
@@ -183,16 +183,21 @@ int32_t enqueue_job(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L) {
       s.ev_contract.push_back(e1);
     }
     HIP_TRY(hipEventRecord(s.ev_contract[2 * pi], st));
-    if (mixed)
-      HIP_TRY(launch_contract_mixed(p.tile.wm, p.tile.wn, p.tile.sc, tasks, tiles + ps.tile0, ps.tile1 - ps.tile0, ws,
-                                    st));
-    else
-      HIP_TRY(launch_contract_f64(p.tile.wm, p.tile.wn, p.tile.sc, tasks, tiles + ps.tile0, ps.tile1 - ps.tile0, ws,
-                                  st));
+    // (ab|P) tiles, then the two-index tiles with their own shape
+    const int ranges[2][2] = {{ps.tile0, ps.tile_mid}, {ps.tile_mid, ps.tile1}};
+    for (int g = 0; g < 2; ++g) {
+      const TileShape& sh = g == 0 ? p.tile : p.tile2;
+      const int n = ranges[g][1] - ranges[g][0];
+      if (n <= 0) continue;
+      if (mixed)
+        HIP_TRY(launch_contract_mixed(sh.wm, sh.wn, sh.sc, tasks, tiles + ranges[g][0], n, ws, st));
+      else
+        HIP_TRY(launch_contract_f64(sh.wm, sh.wn, sh.sc, tasks, tiles + ranges[g][0], n, ws, st));
+    }
     HIP_TRY(hipEventRecord(s.ev_contract[2 * pi + 1], st));
     s.n_contract++;
     for (auto& ph : ps.red_by_phase) {
-      HIP_TRY(launch_reduce(p.tile.wm, p.tile.wn, tasks, reds, items + item_pos, (int)ph.size(), ws, st));
+      HIP_TRY(launch_reduce(tasks, reds, items + item_pos, (int)ph.size(), ws, st));
       item_pos += ph.size();
     }
   }

@@ -1,0 +1,104 @@
+// Contraction tile-shape autotuner (ps_autotune).  Every candidate tiling plans the job again (tile
+// lists, K-splits and workspace depend on the shape) and runs its device work on the context's
+// synchronous slot without copying outputs; the device time between the job's first and last kernel
+// decides.  The winner stays on the context, as ps_set_tiling would leave it.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <string>
+
+#include "jobs.h"
+
+using namespace psint;
+
+namespace {
+
+// Work-group tile (wm, wn) x stage chunks; ksplit 0 lets the planner size the K-splits to the device.
+const int kCandidates[][3] = {{4, 4, 1}, {4, 4, 2}, {4, 2, 1}, {4, 2, 2},
+                              {2, 4, 1}, {2, 4, 2}, {2, 2, 1}, {2, 2, 2}};
+
+int32_t time_candidate(ps_ctx* ctx, const ps_job* job, int reps, ps_tuning* out) {
+  Slot& s = ctx->sync_slot;
+  Plan plan;
+  Layout L;
+  int32_t rc = prepare_slot(ctx, s, job, plan, L);
+  if (rc) return rc;
+  out->device_ms = DBL_MAX;
+  out->contract_ms = DBL_MAX;
+  for (int r = 0; r < reps; ++r) {
+    rc = enqueue_job(ctx, s, plan, L);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(s.stream);
+    if (e != hipSuccess) {
+      ctx->err = std::string("autotune: ") + hipGetErrorString(e);
+      return PS_E_DEVICE;
+    }
+    ps_job_stats st;
+    finish_stats(ctx, s, plan, L, &st, 0.0, 0.0);
+    if (st.device_ms < out->device_ms) {
+      out->device_ms = st.device_ms;
+      out->contract_ms = st.contract_ms;
+    }
+  }
+  return PS_OK;
+}
+
+}  // namespace
+
+extern "C" int32_t ps_autotune(ps_ctx* ctx, const ps_job* job, int32_t reps, ps_tuning* best, ps_tuning* table,
+                               int32_t max_table, int32_t* n_table) {
+  if (!ctx) return PS_E_INVALID;
+  if (!job || !best || reps < 1 || (max_table > 0 && !table)) {
+    ctx->err = "autotune: job and best must be given, reps >= 1";
+    return PS_E_INVALID;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
+  const TileShape saved = ctx->shape;
+  const int saved_ksplit = ctx->ksplit;
+  ps_tuning win{};
+  win.device_ms = DBL_MAX;
+  int n = 0;
+  int32_t first_err = PS_OK;
+  std::string first_msg;
+  for (const auto& c : kCandidates) {
+    ctx->shape.wm = c[0];
+    ctx->shape.wn = c[1];
+    ctx->shape.sc = c[2];
+    ctx->ksplit = 0;
+    ps_tuning t{};
+    t.wm = c[0];
+    t.wn = c[1];
+    t.stage_chunks = c[2];
+    t.ksplit = 0;
+    int32_t rc = time_candidate(ctx, job, reps, &t);
+    if (rc == PS_E_INVALID || rc == PS_E_UNSUPPORTED || rc == PS_E_DEVICE) {
+      // the job itself is at fault (or the device is): no candidate can succeed
+      ctx->shape = saved;
+      ctx->ksplit = saved_ksplit;
+      return rc;
+    }
+    if (rc != PS_OK) {  // this shape's workspace does not fit the budget: skip it
+      if (first_err == PS_OK) {
+        first_err = rc;
+        first_msg = ctx->err;
+      }
+      continue;
+    }
+    if (table && n < max_table) table[n] = t;
+    ++n;
+    if (t.device_ms < win.device_ms) win = t;
+  }
+  if (n_table) *n_table = n < max_table ? n : max_table;
+  if (n == 0) {
+    ctx->shape = saved;
+    ctx->ksplit = saved_ksplit;
+    ctx->err = first_msg;
+    return first_err;
+  }
+  ctx->shape.wm = win.wm;
+  ctx->shape.wn = win.wn;
+  ctx->shape.sc = win.stage_chunks;
+  ctx->ksplit = win.ksplit;
+  *best = win;
+  return PS_OK;
+}

@@ -353,20 +353,24 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
   constexpr int NCUV = (MAXUV * SLOTS + 255) / 256;  // copies per thread per stage, U+V region (max)
   constexpr int NCY = (BN * SLOTS + 255) / 256;      // Y region (max)
   constexpr int KSTEPS = KS / 4;
+  // MFMA steps over which the next stage's copies are issued: FP64 steps are long enough to hide them
+  // in the first two; the FP32 steps are half as long, so they spread over all (measured best)
+  constexpr int CSPREAD = (sizeof(T) == 8 && KSTEPS > 2) ? 2 : KSTEPS;
   constexpr bool F64 = sizeof(T) == 8;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform, lets tests below be scalar
   const int wm = wave >> 1, wn = wave & 1;
   const int kl = lane >> 4;
 
+  // Rows beyond nrows and columns beyond np are computed on whatever their (in-bounds) LDS rows hold
+  // and never read back: an MFMA output row depends only on its A row and an output column only on
+  // its B column, and the reduction skips both.  So the operands need no masking.
   int offU[WM], offV[WM];
-  bool valid[WM];
 #pragma unroll
   for (int mb = 0; mb < WM; ++mb) {
     const int row = wm * 16 * WM + mb * 16 + (lane & 15);
-    valid[mb] = row < t.nrows;
     int u = t.ulo, v = t.vlo;
-    if (valid[mb]) {
+    if (row < t.nrows) {
       u = Tk.pairs[2 * (t.row0 + row)];
       v = Tk.pairs[2 * (t.row0 + row) + 1];
     }
@@ -374,11 +378,9 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
     offV[mb] = (t.nu + v - t.vlo) * LDK + kl;
   }
   int offY[WN];
-  bool ycol[WN];
 #pragma unroll
   for (int nb = 0; nb < WN; ++nb) {
     const int col = wn * 16 * WN + nb * 16 + (lane & 15);
-    ycol[nb] = col < t.np;
     offY[nb] = (MAXUV + col) * LDK + kl;
   }
 
@@ -479,9 +481,9 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
       if (kk + 1 < KSTEPS) fetch(kk + 1, sl ^ 1);
       T av[WM], bv[WN];
 #pragma unroll
-      for (int mb = 0; mb < WM; ++mb) av[mb] = valid[mb] ? uA[sl][mb] * vA[sl][mb] : (T)0;
+      for (int mb = 0; mb < WM; ++mb) av[mb] = uA[sl][mb] * vA[sl][mb];
 #pragma unroll
-      for (int nb = 0; nb < WN; ++nb) bv[nb] = ycol[nb] ? yB[sl][nb] : (T)0;
+      for (int nb = 0; nb < WN; ++nb) bv[nb] = yB[sl][nb];
 #pragma unroll
       for (int mb = 0; mb < WM; ++mb)
 #pragma unroll
@@ -495,7 +497,7 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
       if (more) {
 #pragma unroll
         for (int i = 0; i < NCUV + NCY; ++i)
-          if (i % KSTEPS == kk) copy(s + 1, i);
+          if (i % CSPREAD == kk) copy(s + 1, i);
       }
     }
     if constexpr (!F64) {
@@ -544,20 +546,21 @@ __global__ __launch_bounds__(256, 1) void contract_mixed(const TaskDev* __restri
   contract_body<float, WM, WN, SC>(tasks[t.task], t, (__attribute__((address_space(3))) float*)smem_f, ws);
 }
 
-// Sum the splits of each reduction item in order and scatter into the FP64 output buffer.
-template <int BM, int BN>
+// Sum the splits of each reduction item in order and scatter into the FP64 output buffer.  Partial
+// tiles are row-major with R.bn columns; consecutive threads take consecutive columns.
 __global__ __launch_bounds__(256) void reduce_kernel(const TaskDev* __restrict__ tasks,
                                                      const RedDev* __restrict__ reds,
                                                      const int32_t* __restrict__ items,
                                                      const double* __restrict__ ws) {
   const RedDev R = reds[items[blockIdx.x]];
   const TaskDev& T = tasks[R.task];
-  for (int e = threadIdx.x; e < BM * BN; e += 256) {
-    const int row = e % BM, col = e / BM;
-    if (row >= R.nrows || col >= R.np) continue;
+  const int64_t tile = (int64_t)R.bm * R.bn;
+  for (int e = threadIdx.x; e < R.nrows * R.bn; e += 256) {
+    const int row = e / R.bn, col = e - row * R.bn;
+    if (col >= R.np) continue;
     double s = 0.0;
-    const double* p = ws + R.ws + row * BN + col;
-    for (int k = 0; k < R.nsplit; ++k) s += p[(int64_t)k * BM * BN];
+    const double* p = ws + R.ws + e;
+    for (int k = 0; k < R.nsplit; ++k) s += p[k * tile];
     const int u = T.pairs[2 * (R.row0 + row)], v = T.pairs[2 * (R.row0 + row) + 1];
     const int y = T.y0 + R.p0 + col;
     const int64_t ia = T.mapU[u], ib = T.mapV[v], ip = T.mapY[y];
@@ -848,19 +851,10 @@ hipError_t launch_contract_mixed(int wm, int wn, int sc, const TaskDev* tasks, c
   return launch_contract_any<float>(wm, wn, sc, tasks, tiles, ntiles, ws, st);
 }
 
-hipError_t launch_reduce(int wm, int wn, const TaskDev* tasks, const RedDev* reds, const int32_t* items, int nitems,
+hipError_t launch_reduce(const TaskDev* tasks, const RedDev* reds, const int32_t* items, int nitems,
                          const double* ws, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
-  if (wm == 4 && wn == 4)
-    hipLaunchKernelGGL((reduce_kernel<128, 128>), dim3(nitems), dim3(256), 0, st, tasks, reds, items, ws);
-  else if (wm == 2 && wn == 2)
-    hipLaunchKernelGGL((reduce_kernel<64, 64>), dim3(nitems), dim3(256), 0, st, tasks, reds, items, ws);
-  else if (wm == 4 && wn == 2)
-    hipLaunchKernelGGL((reduce_kernel<128, 64>), dim3(nitems), dim3(256), 0, st, tasks, reds, items, ws);
-  else if (wm == 2 && wn == 4)
-    hipLaunchKernelGGL((reduce_kernel<64, 128>), dim3(nitems), dim3(256), 0, st, tasks, reds, items, ws);
-  else
-    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(reduce_kernel, dim3(nitems), dim3(256), 0, st, tasks, reds, items, ws);
   return hipGetLastError();
 }
 

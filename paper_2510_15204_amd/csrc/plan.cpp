@@ -370,6 +370,9 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
   Plan& p = *P;
   p = Plan();
   p.tile = shape;
+  p.tile2 = shape;
+  p.tile2.wm = 2;
+  p.tile2.wn = 2;
   p.ksplit_override = ksplit_override;
   p.atoms.assign(job->atoms, job->atoms + job->n_atoms);
   if (job->n_bf) p.basis.assign(job->basis, job->basis + job->n_bf);
@@ -816,14 +819,16 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
   }
 
   // ---- passes: group grids so that arrays + workspace fit the budget ----
-  const int BM = shape.bm(), BN = shape.bn(), MAXUV = shape.maxuv();
+  const TileShape& shape2 = p.tile2;
   const size_t es = p.elem_size;
   std::vector<size_t> grid_bytes(p.grids.size(), 0);
   for (auto& a : p.arrays) grid_bytes[a.grid] += (size_t)a.nf * p.grids[a.grid].dev.npad * es;
   // reserve room for the partial tiles of a pass (about 2048 work-groups plus one per tile item) and
   // the output buffer; the rest holds the arrays of the pass's grids
   const size_t out_bytes = (size_t)p.out_elems * 8;
-  const size_t ws_cap = std::min<size_t>((size_t)4096 * BM * BN * 8, budget / 4);
+  const size_t ws_cap1 = std::min<size_t>((size_t)4096 * shape.bm() * shape.bn() * 8, budget / 4);
+  const size_t ws_cap2 = std::min<size_t>((size_t)4096 * shape2.bm() * shape2.bn() * 8, budget / 16);
+  const size_t ws_cap = ws_cap1 + ws_cap2;
   size_t arr_budget = budget > ws_cap + out_bytes ? budget - ws_cap - out_bytes : 0;
   {
     int g0 = 0;
@@ -882,15 +887,19 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       ps.task0 = (int)ti;
       while (ti < p.tasks.size() && p.tasks[ti].grid < ps.grid1) ++ti;
       ps.task1 = (int)ti;
-      // row x column tiles of each task
+      // row x column tiles of each task; group 0 = (ab|P) tasks (main shape), group 1 = two-index
+      // tasks (second shape), each group one contraction launch
       struct Item {
         int task, row0, nrows, p0, np, ulo, nu, vlo, nv;
         double cost;
       };
-      std::vector<Item> items;
-      double total_cost = 0.0;
+      std::vector<Item> items[2];
+      double total_cost[2] = {0.0, 0.0};
       for (int t = ps.task0; t < ps.task1; ++t) {
         TaskHost& th = p.tasks[t];
+        const int grp = th.out_kind == 4 ? 0 : 1;
+        const TileShape& sh = grp == 0 ? shape : shape2;
+        const int BM = sh.bm(), BN = sh.bn(), MAXUV = sh.maxuv();
         const int32_t* pr = p.ints.data() + th.pairs_off;
         const int npairs = th.dev.npairs;
         const int64_t nch = p.grids[th.grid].dev.npad / KC;
@@ -938,63 +947,71 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
             it.vlo = vmin;
             it.nv = vmax - vmin + 1;
             it.cost = (double)nch;
-            total_cost += it.cost;
-            items.push_back(it);
+            total_cost[grp] += it.cost;
+            items[grp].push_back(it);
           }
         }
       }
-      // K splits: aim for about 8 work-groups per CU in total over 256 CUs, within the workspace
-      // reservation (one BM x BN FP64 partial tile per work-group)
-      const double ws_tiles = (double)ws_cap / ((double)BM * BN * 8);
-      const double target = std::max((double)items.size(), std::min(2048.0, ws_tiles));
       int64_t ws = 0;
-      ps.tile0 = (int)p.tiles.size();
       ps.red_by_phase.clear();
-      for (auto& it : items) {
-        TaskHost& th = p.tasks[it.task];
-        const int64_t nch = p.grids[th.grid].dev.npad / KC;
-        int64_t ns;
-        if (p.ksplit_override > 0)
-          ns = p.ksplit_override;
-        else
-          ns = (int64_t)std::llround(target * it.cost / std::max(total_cost, 1.0));
-        const int64_t nst = nch / TileShape::SC_MAX;  // whole stages (nch is a multiple of 16)
-        ns = std::max<int64_t>(1, std::min<int64_t>(ns, std::max<int64_t>(1, nst / 8)));
-        RedDev rd;
-        rd.task = it.task;
-        rd.row0 = it.row0;
-        rd.nrows = it.nrows;
-        rd.p0 = it.p0;
-        rd.np = it.np;
-        rd.nsplit = (int)ns;
-        rd.ws = ws;
-        for (int64_t s = 0; s < ns; ++s) {
-          TileDev td;
-          std::memset(&td, 0, sizeof td);
-          td.task = it.task;
-          td.row0 = it.row0;
-          td.nrows = it.nrows;
-          td.ulo = it.ulo;
-          td.nu = it.nu;
-          td.vlo = it.vlo;
-          td.nv = it.nv;
-          td.p0 = it.p0;
-          td.np = it.np;
-          td.kc0 = TileShape::SC_MAX * (nst * s / ns);
-          td.nkc = TileShape::SC_MAX * (nst * (s + 1) / ns) - td.kc0;
-          td.ws = ws + s * (int64_t)BM * BN;
-          p.issued_flops += 2.0 * BM * BN * (double)td.nkc * KC;
-          p.tiles.push_back(td);
+      ps.tile0 = (int)p.tiles.size();
+      for (int grp = 0; grp < 2; ++grp) {
+        if (grp == 1) ps.tile_mid = (int)p.tiles.size();
+        const TileShape& sh = grp == 0 ? shape : shape2;
+        const int BM = sh.bm(), BN = sh.bn();
+        // K splits: aim for about 8 work-groups per CU over 256 CUs per launch, within the group's
+        // workspace reservation (one BM x BN FP64 partial tile per work-group)
+        const double ws_tiles = (double)(grp == 0 ? ws_cap1 : ws_cap2) / ((double)BM * BN * 8);
+        const double target = std::max((double)items[grp].size(), std::min(2048.0, ws_tiles));
+        const int tg0 = (int)p.tiles.size();
+        for (auto& it : items[grp]) {
+          TaskHost& th = p.tasks[it.task];
+          const int64_t nch = p.grids[th.grid].dev.npad / KC;
+          int64_t ns;
+          if (p.ksplit_override > 0)
+            ns = p.ksplit_override;
+          else
+            ns = (int64_t)std::llround(target * it.cost / std::max(total_cost[grp], 1.0));
+          const int64_t nst = nch / TileShape::SC_MAX;  // whole stages (nch is a multiple of 16)
+          ns = std::max<int64_t>(1, std::min<int64_t>(ns, std::max<int64_t>(1, nst / 8)));
+          RedDev rd;
+          rd.task = it.task;
+          rd.row0 = it.row0;
+          rd.nrows = it.nrows;
+          rd.p0 = it.p0;
+          rd.np = it.np;
+          rd.nsplit = (int)ns;
+          rd.bm = BM;
+          rd.bn = BN;
+          rd.ws = ws;
+          for (int64_t sp = 0; sp < ns; ++sp) {
+            TileDev td;
+            std::memset(&td, 0, sizeof td);
+            td.task = it.task;
+            td.row0 = it.row0;
+            td.nrows = it.nrows;
+            td.ulo = it.ulo;
+            td.nu = it.nu;
+            td.vlo = it.vlo;
+            td.nv = it.nv;
+            td.p0 = it.p0;
+            td.np = it.np;
+            td.kc0 = TileShape::SC_MAX * (nst * sp / ns);
+            td.nkc = TileShape::SC_MAX * (nst * (sp + 1) / ns) - td.kc0;
+            td.ws = ws + sp * (int64_t)BM * BN;
+            p.issued_flops += 2.0 * BM * BN * (double)td.nkc * KC;
+            p.tiles.push_back(td);
+          }
+          ws += ns * (int64_t)BM * BN;
+          int phase = th.phase;
+          if ((int)ps.red_by_phase.size() <= phase) ps.red_by_phase.resize(phase + 1);
+          ps.red_by_phase[phase].push_back((int)p.reds.size());
+          p.reds.push_back(rd);
         }
-        ws += ns * (int64_t)BM * BN;
-        int phase = th.phase;
-        if ((int)ps.red_by_phase.size() <= phase) ps.red_by_phase.resize(phase + 1);
-        ps.red_by_phase[phase].push_back((int)p.reds.size());
-        p.reds.push_back(rd);
+        xcd_order(p.tiles, tg0, (int)p.tiles.size());
       }
       ps.tile1 = (int)p.tiles.size();
       ps.ws_elems = (size_t)ws;
-      xcd_order(p.tiles, ps.tile0, ps.tile1);
       p.max_ws_bytes = std::max(p.max_ws_bytes, (size_t)ws * 8);
     }
   }

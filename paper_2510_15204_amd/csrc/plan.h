@@ -59,7 +59,8 @@ struct Pass {
   int grid0, grid1;     // grids [grid0, grid1)
   int seg0, seg1;       // segments
   int task0, task1;     // tasks
-  int tile0, tile1;     // tiles
+  int tile0, tile1;     // tiles: [tile0, tile_mid) main shape, [tile_mid, tile1) the two-index shape
+  int tile_mid;
   std::vector<std::vector<int>> red_by_phase;  // reduce item ids per phase
   int64_t eval_blocks;
   size_t array_bytes;
@@ -72,7 +73,9 @@ struct Plan {
   std::vector<ps_sto> basis, aux;
   int n_bf = 0, n_aux = 0, n_atoms = 0;
   int precision = 0;
-  TileShape tile;
+  TileShape tile;        // (ab|P) tasks
+  TileShape tile2;       // two-index tasks (S, T, V, (P|Q)): a smaller tile wastes less on their short
+                         // column ranges (one atom's basis or auxiliary functions)
   int ksplit_override = 0;
 
   std::vector<GridHost> grids;

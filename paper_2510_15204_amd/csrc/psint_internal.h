@@ -115,7 +115,8 @@ struct RedDev {
   int32_t task;
   int32_t row0, nrows, p0, np;
   int32_t nsplit;
-  int64_t ws;            // workspace offset of split 0; split s at ws + s * BM * BN
+  int32_t bm, bn;        // tile shape of the item's partial tiles (row-major, bn columns)
+  int64_t ws;            // workspace offset of split 0; split s at ws + s * bm * bn
 };
 
 }  // namespace psint

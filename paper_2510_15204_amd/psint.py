@@ -68,6 +68,14 @@ class JobStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Tuning(C.Structure):
+    _fields_ = [("wm", C.c_int32), ("wn", C.c_int32), ("stage_chunks", C.c_int32), ("ksplit", C.c_int32),
+                ("device_ms", C.c_double), ("contract_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _LIB = None
 
 
@@ -98,12 +106,14 @@ def lib():
         L.ps_plan_work.argtypes = [vp, C.POINTER(Job), _dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_size_t)]
         L.ps_set_tiling.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+        L.ps_autotune.argtypes = [vp, C.POINTER(Job), C.c_int32, C.POINTER(Tuning), C.POINTER(Tuning), C.c_int32,
+                                  C.POINTER(C.c_int32)]
         L.ps_status_string.argtypes = [C.c_int32]
         L.ps_status_string.restype = C.c_char_p
         L.ps_last_error.argtypes = [vp]
         L.ps_last_error.restype = C.c_char_p
         for f in ("ps_create", "ps_destroy", "ps_compute", "ps_submit", "ps_wait", "ps_grid_points",
-                  "ps_eval_function", "ps_plan_work", "ps_set_tiling"):
+                  "ps_eval_function", "ps_plan_work", "ps_set_tiling", "ps_autotune"):
             getattr(L, f).restype = C.c_int32
         _LIB = L
     return _LIB
@@ -123,7 +133,8 @@ def plan_work_host(job, precision=None):
 
 def exported_symbols():
     return ["ps_create", "ps_destroy", "ps_compute", "ps_submit", "ps_wait", "ps_grid_points",
-            "ps_eval_function", "ps_plan_work", "ps_set_tiling", "ps_status_string", "ps_last_error"]
+            "ps_eval_function", "ps_plan_work", "ps_set_tiling", "ps_autotune", "ps_status_string",
+            "ps_last_error"]
 
 
 def _spec(s) -> GridSpec:
@@ -212,6 +223,16 @@ class Context:
 
     def set_tiling(self, wm=0, wn=0, stage_chunks=0, ksplit=0):
         self._check(lib().ps_set_tiling(self.h, wm, wn, stage_chunks, ksplit))
+
+    def autotune(self, job, precision=None, reps=1):
+        """Time every candidate contraction tiling on `job` (ps_autotune); the fastest stays set on
+        the context.  Returns (best, table) as dicts."""
+        ref = _JobRef(job, precision)
+        best = Tuning()
+        table = (Tuning * 16)()
+        n = C.c_int32()
+        self._check(lib().ps_autotune(self.h, C.byref(ref.j), reps, C.byref(best), table, 16, C.byref(n)))
+        return best.as_dict(), [table[i].as_dict() for i in range(n.value)]
 
     def plan_work(self, job, precision=None):
         ref = _JobRef(job, precision)

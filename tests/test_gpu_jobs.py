@@ -240,3 +240,31 @@ def test_memory_passes_match_single_pass():
         scale = max(np.max(np.abs(ref[k])), 1e-300)
         assert np.max(np.abs(got[k] - ref[k])) <= 1e-12 * scale, k
     big.close()
+
+
+def test_autotune_selects_fastest_and_keeps_results():
+    """ps_autotune times every candidate tiling, leaves the fastest on the context, and a job run with
+    it agrees with the default tiling (up to the summation order of the point splits) and the oracle."""
+    job = _tri_tz((10, 10, 8, 4, 3, 2.3, 0.25))
+    c = psint.Context(0)
+    ref, _, _ = c.compute(job)
+    best, table = c.autotune(job, reps=2)
+    _say("autotune: " + "; ".join(f"{t['wm']}x{t['wn']}x{t['stage_chunks']} {t['device_ms']:.3f} ms"
+                                  for t in table))
+    assert len(table) == 8
+    assert best["device_ms"] == min(t["device_ms"] for t in table)
+    assert all(t["device_ms"] > 0 and 0 < t["contract_ms"] <= t["device_ms"] for t in table)
+    got, st, rc = c.compute(job)
+    for k in KINDS:
+        scale = max(np.max(np.abs(ref[k])), 1e-300)
+        assert np.max(np.abs(got[k] - ref[k])) <= 1e-12 * scale, k
+    # this auxiliary metric is ill-conditioned, so the factor amplifies last-bit differences of (P|Q);
+    # check it as a factor of the (P|Q) it came with
+    if rc == psint.PS_OK:
+        L = got["PQ_chol"]
+        assert np.max(np.abs(L @ L.T - got["PQ"])) < 1e-12 * np.max(np.abs(got["PQ"]))
+    orc = O.compute_full(job)
+    assert max(np.max(np.abs(got[k] - orc[k])) for k in KINDS) < 1e-10
+    with pytest.raises(psint.PsError):
+        c.autotune(job, reps=0)
+    c.close()
