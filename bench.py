@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=15000, help="abP elements in the oracle sample")
     ap.add_argument("--tiling", default="0,0,0,0", help="wm,wn,stage_chunks,ksplit (0 = library default)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "contract_traffic.json"))
+    ap.add_argument("--no-ri", action="store_true", help="skip the RI-assembly measurement after the steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     return ap.parse_args()
@@ -153,6 +154,8 @@ def main():
            "roofline": roofline}
     if tuning:
         out["autotune"] = tuning
+    if not args.no_ri:
+        out["ri_assembly"] = ri_leg(ctx, outs, rc, psint)
     if not args.no_cpu_baseline:
         import oracle as O
         rng = np.random.default_rng(15204)
@@ -174,6 +177,29 @@ def main():
                                          f"{wpp:.3e} pair-points in {cdt:.1f} s"}
         out["error_vs_fp64_oracle"] = err
     print(json.dumps(out), flush=True)
+
+
+def ri_leg(ctx, outs, rc, psint, reps=3):
+    """RI assembly (eq. 14) on the job's (ab|P) and (P|Q) factor, after the timed steps.  When the
+    synthetic auxiliary metric is not positive definite at this grid, the factor of (P|Q) + eps I
+    (eps = 1e-5 of its largest diagonal element) stands in; the kernels' work does not depend on it."""
+    import torch
+    abP, L = outs["abP"], outs["PQ_chol"]
+    note = "factor of the job's (P|Q)"
+    if rc != psint.PS_OK:
+        PQ = outs["PQ"].cpu().numpy()
+        eps = 1e-5 * float(np.max(np.diag(PQ)))
+        L = torch.from_numpy(np.linalg.cholesky(PQ + eps * np.eye(PQ.shape[0]))).to(abP.device)
+        note = f"(P|Q) not positive definite at this grid; factor of (P|Q) + {eps:.2e} I"
+    na, nb = abP.shape[0], abP.shape[1]
+    npair = nb * (nb + 1) // 2
+    ctx.ri_assemble(abP, L)  # warm-up (allocates the scratch)
+    ms = [ctx.ri_assemble(abP, L)[2] for _ in range(reps)]
+    syrk = float(npair) * (npair + 1) * na  # 2 FLOPs per multiply-add over the upper triangle
+    trsm = float(na) * na * npair
+    t = float(np.mean(ms)) / 1e3
+    return {"inputs": note, "n_pair": npair, "n_aux": na, "ms": t * 1e3, "flops": syrk + trsm,
+            "achieved_tflops": (syrk + trsm) / t / 1e12, "frac_fp64_peak": (syrk + trsm) / t / PEAK["fp64"]}
 
 
 def serve_bench(args, torch, psint, W):

@@ -175,6 +175,20 @@ typedef struct {
 int32_t ps_autotune(ps_ctx* ctx, const ps_job* job, int32_t reps, ps_tuning* best, ps_tuning* table,
                     int32_t max_table, int32_t* n_table);
 
+/* ---- RI assembly (eq. 14) ------------------------------------------------------------------ */
+/* The paper's RI form of the electron-repulsion integrals, (ab|cd) ~ sum_PQ (ab|P) [(P|Q)^-1] (Q|cd),
+ * evaluated through the Cholesky factor (P|Q) = L L^T:
+ *   B[R][ab]   = sum_P (L^-1)[R][P] (ab|P)     (forward substitution, FP64)
+ *   eri[ab][cd] = sum_R B[R][ab] B[R][cd]      (FP64 MFMA, symmetric)
+ * over canonical pairs a >= b, ab = a(a+1)/2 + b, n_pair = n_bf(n_bf+1)/2.
+ * Inputs as ps_compute writes them: abP [P][a][b] (n_aux x n_bf x n_bf), L n_aux x n_aux lower
+ * (the upper triangle is not read).  Outputs (NULL = not wanted): B n_aux x n_pair and eri
+ * n_pair x n_pair, row-major FP64.  All four arrays live on the host (location PS_OUT_HOST) or on
+ * the context's device (PS_OUT_DEVICE); device scratch (grown on demand, freed by ps_destroy) must
+ * fit the context's budget, else PS_E_NOMEM.  *device_ms (may be NULL) receives the kernels' time. */
+int32_t ps_ri_assemble(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, int32_t location, const double* abP,
+                       const double* L, double* B, double* eri, double* device_ms);
+
 const char* ps_status_string(int32_t status);
 /* Last error text of the context (valid until the next call on it); ctx may be NULL. */
 const char* ps_last_error(ps_ctx* ctx);

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpsint.so")
-SOURCES = ["kernels.hip", "plan.cpp", "api.cpp", "serve.cpp", "autotune.cpp"]
+SOURCES = ["kernels.hip", "ri.hip", "plan.cpp", "api.cpp", "serve.cpp", "autotune.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          # no packed FP32 instructions (see the packed-math note in the design document)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

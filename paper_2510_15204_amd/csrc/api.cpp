@@ -393,6 +393,7 @@ int32_t ps_destroy(ps_ctx* ctx) {
   serve_shutdown(ctx);
   (void)hipSetDevice(ctx->device);
   slot_free(ctx->sync_slot);
+  if (ctx->ri_buf) (void)hipFree(ctx->ri_buf);
   delete ctx;
   return PS_OK;
 }

@@ -45,6 +45,8 @@ struct ps_ctx {
   int ksplit = 0;
   psint::Slot sync_slot;
   psint::ServeState* serve = nullptr;  // created by the first ps_submit, freed by ps_destroy
+  void* ri_buf = nullptr;              // RI assembly scratch (grown on demand)
+  size_t ri_buf_size = 0;
 };
 
 namespace psint {

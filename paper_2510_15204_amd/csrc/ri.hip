@@ -1,0 +1,354 @@
+// RI assembly (eq. 14): B = L^-1 A with A[P][ab] = (ab|P) over canonical pairs a >= b, then the
+// electron-repulsion matrix eri[ab][cd] = sum_R B[R][ab] B[R][cd].  Three kernels, all FP64:
+//   ri_gather_kernel  (ab|P) [P][a][b] -> A [P][ab]                 (HBM-bound copy)
+//   ri_inv_kernel     inverses of the 32 x 32 diagonal blocks of L (substitution, one per work-group)
+//   ri_offdiag_kernel L times those inverses below the diagonal blocks
+//   ri_solve_kernel   one block step of the forward substitution as a product on FP64 MFMA
+//   ri_syrk_kernel    64 x 64 output tiles on or above the diagonal, v_mfma_f64_16x16x4f64 with the
+//                     16-row slices of B staged in LDS; the mirror tile is written through an LDS
+//                     transpose so both halves are stored with coalesced rows
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+
+namespace psint {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void ri_gather_kernel(const double* __restrict__ abP, int nb, int na,
+                                                        double* __restrict__ A) {
+  const int64_t npair = (int64_t)nb * (nb + 1) / 2;
+  const int64_t total = (int64_t)na * nb * nb;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t P = e / ((int64_t)nb * nb);
+    const int rem = (int)(e - P * nb * nb);
+    const int a = rem / nb, b = rem - a * nb;
+    if (b > a) continue;
+    A[P * npair + (int64_t)a * (a + 1) / 2 + b] = abP[e];
+  }
+}
+
+constexpr int TR_ROWS = 32;  // rows of B per block step of the forward substitution
+
+// Blocked forward substitution with inverted diagonal blocks.  With D_k the inverse of the k-th
+// 32 x 32 diagonal block of L, the transformed factor G holds G_kk = D_k and, below the diagonal
+// blocks, G_ik = L_ik D_k.  Then block step k is one product with the not-yet-solved rows X_k:
+//   B_k = G_kk X_k        and        X_i -= G_ik X_k for every block row i below k.
+
+// G_kk = D_k by substitution, row by row: lane j computes D[r][j] for every row r in turn (one block
+// per work-group of one wave); the rows solved so far stay in LDS.
+__global__ __launch_bounds__(64) void ri_inv_kernel(const double* __restrict__ L, int na, double* __restrict__ G) {
+  __shared__ double Ld[TR_ROWS][TR_ROWS];
+  __shared__ double Dk[TR_ROWS][TR_ROWS + 1];
+  const int r0 = blockIdx.x * TR_ROWS, nr = min(TR_ROWS, na - r0);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < TR_ROWS * TR_ROWS; e += 64) {
+    const int r = e / TR_ROWS, q = e - r * TR_ROWS;
+    Ld[r][q] = (r < nr && q < nr) ? L[(int64_t)(r0 + r) * na + r0 + q] : (r == q ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  const int j = tid & (TR_ROWS - 1);
+  for (int r = 0; r < TR_ROWS; ++r) {
+    double v = r == j ? 1.0 : 0.0;
+    for (int q = j; q < r; ++q) v -= Ld[r][q] * Dk[q][j];
+    if (tid < TR_ROWS) Dk[r][j] = v / Ld[r][r];
+    __syncthreads();
+  }
+  for (int e = tid; e < TR_ROWS * TR_ROWS; e += 64) {
+    const int r = e / TR_ROWS, q = e - r * TR_ROWS;
+    if (r < nr && q < nr) G[(int64_t)(r0 + r) * na + r0 + q] = q <= r ? Dk[r][q] : 0.0;
+  }
+}
+
+// G_ik = L_ik D_k for every element (i, c) whose column block lies left of row i's block.
+__global__ __launch_bounds__(256) void ri_offdiag_kernel(const double* __restrict__ L, int na, double* __restrict__ G) {
+  const int64_t total = (int64_t)na * na;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / na), c = (int)(e - (int64_t)i * na);
+    const int k = c / TR_ROWS, r0 = k * TR_ROWS;
+    if (i < r0 + TR_ROWS) continue;  // on or above the diagonal blocks
+    const int nr = min(TR_ROWS, na - r0), sc = c - r0;
+    double v = 0.0;
+    for (int t = sc; t < nr; ++t) v += L[(int64_t)i * na + r0 + t] * G[(int64_t)(r0 + t) * na + c];
+    G[e] = v;
+  }
+}
+
+constexpr int UP_T = 64;  // solve tile: 64 rows x 64 columns, K = the 32 rows of block k
+
+// Block step k on FP64 MFMA.  blockIdx.y == 0: B[r0 .. r0 + nr) = G_kk X_k; blockIdx.y >= 1: a
+// 64-row tile below the block, X_i -= G_ik X_k.  X rows of block k are only read in this launch.
+__global__ __launch_bounds__(256) void ri_solve_kernel(const double* __restrict__ G, int na, int64_t n,
+                                                      double* __restrict__ X, double* __restrict__ Bo, int r0) {
+  __shared__ double As[TR_ROWS][UP_T + 1], Bs[TR_ROWS][UP_T];
+  const int nr = min(TR_ROWS, na - r0);
+  const bool diag = blockIdx.y == 0;
+  const int64_t i0 = diag ? r0 : r0 + nr + (int64_t)(blockIdx.y - 1) * UP_T;
+  const int64_t iend = diag ? r0 + nr : na;
+  const int64_t c0 = (int64_t)blockIdx.x * UP_T;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wi = wave >> 1, wj = wave & 1, kl = lane >> 4, lc = lane & 15;
+  for (int e = tid; e < UP_T * TR_ROWS; e += 256) {
+    const int ii = e / TR_ROWS, k = e - ii * TR_ROWS;  // reads along G's rows
+    As[k][ii] = (i0 + ii < iend && k < nr) ? G[(i0 + ii) * na + r0 + k] : 0.0;
+  }
+  for (int e = tid; e < TR_ROWS * UP_T; e += 256) {
+    const int k = e / UP_T, c = e - k * UP_T;
+    Bs[k][c] = (k < nr && c0 + c < n) ? X[(int64_t)(r0 + k) * n + c0 + c] : 0.0;
+  }
+  __syncthreads();
+  d4_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (d4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < TR_ROWS / 4; ++s) {
+    double av[2], bv[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) av[m] = As[4 * s + kl][wi * 32 + m * 16 + lc];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) bv[m] = Bs[4 * s + kl][wj * 32 + m * 16 + lc];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = i0 + wi * 32 + a * 16 + 4 * r + kl, col = c0 + wj * 32 + b * 16 + lc;
+        if (row < iend && col < n) {
+          if (diag)
+            Bo[row * n + col] = acc[a][b][r];
+          else
+            X[row * n + col] -= acc[a][b][r];
+        }
+      }
+}
+
+constexpr int SY_T = 64;   // output tile
+constexpr int SY_K = 16;   // rows of B per stage
+
+// C = X^T X for X (nk x n, row-major); tile list holds (ti, tj) with ti <= tj.
+__global__ __launch_bounds__(256) void ri_syrk_kernel(const double* __restrict__ X, int nk, int64_t n,
+                                                     const int2* __restrict__ tiles, double* __restrict__ C) {
+  __shared__ double As[SY_K][SY_T], Bs[SY_K][SY_T];
+  __shared__ double Ct[SY_T][SY_T + 1];
+  const int2 tl = tiles[blockIdx.x];
+  const int64_t i0 = (int64_t)tl.x * SY_T, j0 = (int64_t)tl.y * SY_T;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wi = wave >> 1, wj = wave & 1, kl = lane >> 4, lc = lane & 15;
+  d4_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (d4_t){0.0, 0.0, 0.0, 0.0};
+  // each thread stages 4 + 4 values of a 16-row slice; the next slice is loaded into registers
+  // while the current one feeds the MFMAs
+  constexpr int PER = SY_K * SY_T / 256;
+  double ra[PER], rb[PER];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q, kk = e / SY_T, c = e - kk * SY_T;
+      const bool kin = k0 + kk < nk;
+      ra[q] = (kin && i0 + c < n) ? X[(int64_t)(k0 + kk) * n + i0 + c] : 0.0;
+      rb[q] = (kin && j0 + c < n) ? X[(int64_t)(k0 + kk) * n + j0 + c] : 0.0;
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < nk; k0 += SY_K) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q, kk = e / SY_T, c = e - kk * SY_T;
+      As[kk][c] = ra[q];
+      Bs[kk][c] = rb[q];
+    }
+    __syncthreads();
+    if (k0 + SY_K < nk) load(k0 + SY_K);
+#pragma unroll
+    for (int s = 0; s < SY_K / 4; ++s) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) av[m] = As[4 * s + kl][wi * 32 + m * 16 + lc];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) bv[m] = Bs[4 * s + kl][wj * 32 + m * 16 + lc];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+  }
+  // tile -> LDS, then row-major stores of the tile and (off the diagonal) of its transpose
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Ct[wi * 32 + a * 16 + 4 * r + kl][wj * 32 + b * 16 + lc] = acc[a][b][r];
+  __syncthreads();
+  for (int e = tid; e < SY_T * SY_T; e += 256) {
+    const int r = e / SY_T, c = e - r * SY_T;
+    if (i0 + r < n && j0 + c < n) C[(i0 + r) * n + j0 + c] = Ct[r][c];
+  }
+  if (tl.x != tl.y) {
+    for (int e = tid; e < SY_T * SY_T; e += 256) {
+      const int c = e / SY_T, r = e - c * SY_T;
+      if (i0 + r < n && j0 + c < n) C[(j0 + c) * n + i0 + r] = Ct[r][c];
+    }
+  }
+}
+
+}  // namespace psint
+
+using namespace psint;
+
+namespace {
+
+int32_t ensure_ri_buffer(ps_ctx* ctx, size_t bytes) {
+  if (ctx->ri_buf_size >= bytes) return PS_OK;
+  if (ctx->ri_buf) (void)hipFree(ctx->ri_buf);
+  ctx->ri_buf = nullptr;
+  ctx->ri_buf_size = 0;
+  hipError_t e = hipMalloc(&ctx->ri_buf, bytes);
+  if (e != hipSuccess) {
+    ctx->ri_buf = nullptr;
+    ctx->err = std::string("ri: hipMalloc: ") + hipGetErrorString(e);
+    return PS_E_NOMEM;
+  }
+  ctx->ri_buf_size = bytes;
+  return PS_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+#define RI_TRY(call)                                              \
+  do {                                                            \
+    hipError_t e_ = (call);                                       \
+    if (e_ != hipSuccess) {                                       \
+      ctx->err = std::string(#call) + ": " + hipGetErrorString(e_); \
+      return PS_E_DEVICE;                                         \
+    }                                                             \
+  } while (0)
+
+extern "C" int32_t ps_ri_assemble(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, int32_t location, const double* abP,
+                                  const double* L, double* B, double* eri, double* device_ms) {
+  if (!ctx) return PS_E_INVALID;
+  if (n_bf < 1 || n_aux < 1 || !abP || !L || (location != PS_OUT_HOST && location != PS_OUT_DEVICE)) {
+    ctx->err = "ri: n_bf, n_aux >= 1, abP and L required, location PS_OUT_HOST or PS_OUT_DEVICE";
+    return PS_E_INVALID;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
+  const bool dev = location == PS_OUT_DEVICE;
+  const int64_t nb = n_bf, na = n_aux, npair = nb * (nb + 1) / 2;
+  const size_t abp_b = (size_t)na * nb * nb * 8, l_b = (size_t)na * na * 8, x_b = (size_t)na * npair * 8,
+               eri_b = (size_t)npair * npair * 8;
+  // scratch: X always; host inputs and host eri staged on the device
+  size_t off_abp = 0, off_l = 0, off_x = 0, off_eri = 0, total = 0;
+  if (!dev) {
+    off_abp = total;
+    total = align256(total + abp_b);
+    off_l = total;
+    total = align256(total + l_b);
+  }
+  off_x = total;
+  total = align256(total + x_b);
+  const size_t off_b = total;
+  total = align256(total + x_b);
+  const size_t off_g = total;
+  total = align256(total + l_b);
+  const size_t ntiles = (size_t)((npair + SY_T - 1) / SY_T) * ((npair + SY_T - 1) / SY_T + 1) / 2;
+  const size_t off_tiles = total;
+  total = align256(total + ntiles * sizeof(int2));
+  if (eri && !dev) {
+    off_eri = total;
+    total = align256(total + eri_b);
+  }
+  if (total > ctx->budget) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "ri: needs %.2f GB of device memory, budget is %.2f GB", total / 1e9, ctx->budget / 1e9);
+    ctx->err = buf;
+    return PS_E_NOMEM;
+  }
+  int32_t rc = ensure_ri_buffer(ctx, total);
+  if (rc) return rc;
+  char* base = (char*)ctx->ri_buf;
+  hipStream_t st = ctx->sync_slot.stream;
+  const double* d_abp = dev ? abP : (const double*)(base + off_abp);
+  const double* d_l = dev ? L : (const double*)(base + off_l);
+  double* d_x = (double*)(base + off_x);
+  double* d_b = (double*)(base + off_b);
+  double* d_g = (double*)(base + off_g);
+  int2* d_tiles = (int2*)(base + off_tiles);
+  double* d_eri = eri ? (dev ? eri : (double*)(base + off_eri)) : nullptr;
+  if (!dev) {
+    RI_TRY(hipMemcpyAsync((void*)d_abp, abP, abp_b, hipMemcpyHostToDevice, st));
+    RI_TRY(hipMemcpyAsync((void*)d_l, L, l_b, hipMemcpyHostToDevice, st));
+  }
+  std::vector<int2> tl;
+  if (eri) {
+    const int nt = (int)((npair + SY_T - 1) / SY_T);
+    tl.reserve(ntiles);
+    for (int i = 0; i < nt; ++i)
+      for (int j = i; j < nt; ++j) tl.push_back(make_int2(i, j));
+    RI_TRY(hipMemcpyAsync(d_tiles, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  }
+  hipEvent_t e0, e1;
+  RI_TRY(hipEventCreate(&e0));
+  RI_TRY(hipEventCreate(&e1));
+  RI_TRY(hipEventRecord(e0, st));
+  {
+    int64_t blocks = (na * nb * nb + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(ri_gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d_abp, n_bf, n_aux, d_x);
+    RI_TRY(hipGetLastError());
+  }
+  // blocked forward substitution on the transformed factor, B into its own buffer
+  {
+    const int nblk = (n_aux + TR_ROWS - 1) / TR_ROWS;
+    hipLaunchKernelGGL(ri_inv_kernel, dim3((unsigned)nblk), dim3(64), 0, st, d_l, n_aux, d_g);
+    RI_TRY(hipGetLastError());
+    int64_t blocks = (na * na + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(ri_offdiag_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d_l, n_aux, d_g);
+    RI_TRY(hipGetLastError());
+    for (int r0 = 0; r0 < n_aux; r0 += TR_ROWS) {
+      const int below = n_aux - std::min(n_aux, r0 + TR_ROWS);
+      hipLaunchKernelGGL(ri_solve_kernel,
+                         dim3((unsigned)((npair + UP_T - 1) / UP_T), (unsigned)(1 + (below + UP_T - 1) / UP_T)),
+                         dim3(256), 0, st, (const double*)d_g, n_aux, npair, d_x, d_b, r0);
+      RI_TRY(hipGetLastError());
+    }
+  }
+  if (eri) {
+    hipLaunchKernelGGL(ri_syrk_kernel, dim3((unsigned)tl.size()), dim3(256), 0, st, (const double*)d_b, n_aux, npair,
+                       (const int2*)d_tiles, d_eri);
+    RI_TRY(hipGetLastError());
+  }
+  RI_TRY(hipEventRecord(e1, st));
+  if (B) RI_TRY(hipMemcpyAsync(B, d_b, x_b, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  if (eri && !dev) RI_TRY(hipMemcpyAsync(eri, d_eri, eri_b, hipMemcpyDeviceToHost, st));
+  RI_TRY(hipStreamSynchronize(st));
+  float ms = 0.0f;
+  RI_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (device_ms) *device_ms = ms;
+  return PS_OK;
+}

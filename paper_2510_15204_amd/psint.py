@@ -108,12 +108,13 @@ def lib():
         L.ps_set_tiling.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.ps_autotune.argtypes = [vp, C.POINTER(Job), C.c_int32, C.POINTER(Tuning), C.POINTER(Tuning), C.c_int32,
                                   C.POINTER(C.c_int32)]
+        L.ps_ri_assemble.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp, _dp]
         L.ps_status_string.argtypes = [C.c_int32]
         L.ps_status_string.restype = C.c_char_p
         L.ps_last_error.argtypes = [vp]
         L.ps_last_error.restype = C.c_char_p
         for f in ("ps_create", "ps_destroy", "ps_compute", "ps_submit", "ps_wait", "ps_grid_points",
-                  "ps_eval_function", "ps_plan_work", "ps_set_tiling", "ps_autotune"):
+                  "ps_eval_function", "ps_plan_work", "ps_set_tiling", "ps_autotune", "ps_ri_assemble"):
             getattr(L, f).restype = C.c_int32
         _LIB = L
     return _LIB
@@ -133,8 +134,8 @@ def plan_work_host(job, precision=None):
 
 def exported_symbols():
     return ["ps_create", "ps_destroy", "ps_compute", "ps_submit", "ps_wait", "ps_grid_points",
-            "ps_eval_function", "ps_plan_work", "ps_set_tiling", "ps_autotune", "ps_status_string",
-            "ps_last_error"]
+            "ps_eval_function", "ps_plan_work", "ps_set_tiling", "ps_autotune", "ps_ri_assemble",
+            "ps_status_string", "ps_last_error"]
 
 
 def _spec(s) -> GridSpec:
@@ -233,6 +234,31 @@ class Context:
         n = C.c_int32()
         self._check(lib().ps_autotune(self.h, C.byref(ref.j), reps, C.byref(best), table, 16, C.byref(n)))
         return best.as_dict(), [table[i].as_dict() for i in range(n.value)]
+
+    def ri_assemble(self, abP, L, want_B=True, want_eri=True):
+        """RI assembly (ps_ri_assemble) on abP [P][a][b] and the lower factor L.  numpy inputs give
+        numpy outputs (host path); torch device tensors give device tensors.  Returns
+        (B or None, eri or None, device_ms)."""
+        na, nb = int(abP.shape[0]), int(abP.shape[1])
+        npair = nb * (nb + 1) // 2
+        dev = not isinstance(abP, np.ndarray)
+        if dev:
+            import torch
+            assert abP.dtype == torch.float64 and L.dtype == torch.float64 and abP.is_cuda and L.is_cuda
+            abP, L = abP.contiguous(), L.contiguous()
+            mk = lambda shape: torch.empty(shape, dtype=torch.float64, device=abP.device)  # noqa: E731
+            ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+        else:
+            abP = np.ascontiguousarray(abP, dtype=np.float64)
+            L = np.ascontiguousarray(L, dtype=np.float64)
+            mk = lambda shape: np.empty(shape)  # noqa: E731
+            ptr = lambda a: C.c_void_p(a.ctypes.data) if a is not None else None  # noqa: E731
+        B = mk((na, npair)) if want_B else None
+        eri = mk((npair, npair)) if want_eri else None
+        ms = C.c_double()
+        self._check(lib().ps_ri_assemble(self.h, nb, na, 1 if dev else 0, ptr(abP), ptr(L), ptr(B), ptr(eri),
+                                         C.byref(ms)))
+        return B, eri, ms.value
 
     def plan_work(self, job, precision=None):
         ref = _JobRef(job, precision)

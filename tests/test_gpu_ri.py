@@ -1,0 +1,116 @@
+"""GPU: RI assembly (eq. 14) through the C ABI against the oracle's forward substitution and product."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import MiniJob, Spec
+from paper_2510_15204_amd import psint
+from paper_2510_15204_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = psint.Context(0)
+    yield c
+    c.close()
+
+
+def _pd_job(n_max_basis=4):
+    """Triatomic with a triple-zeta-sized basis (43 functions, 946 pairs: 14 full 64-pair tiles and a
+    ragged one) and 75 well-separated auxiliary functions ((P|Q) condition number about 2e4; 75 = two
+    32-row blocks plus a ragged 11)."""
+    rng = W.rng_for(1)
+    Z = np.array([8.0, 1.0, 1.0])
+    basis, _ = W.build_basis(rng, Z.astype(int), "TZ", "auxTZ", n_max=n_max_basis)
+    aux = []
+    for a in range(3):
+        aux += [[a, 1, 0, 0, z] for z in (9.0, 3.0, 1.0)]
+        aux += [[a, 2, 1, m, z] for z in (4.0, 1.5) for m in (-1, 0, 1)]
+        aux += [[a, 3, 2, m, 2.5] for m in range(-2, 3)]
+        aux += [[a, 4, 3, m, 2.2] for m in range(-3, 4)]
+    aux += [[0, 3, 2, m, 1.2] for m in range(-2, 3)] + [[1, 4, 3, m, 1.4] for m in range(-3, 4)]
+    return MiniJob(W.triatomic_geometry(), Z, basis, aux, Spec(10, 10, 8, 4, 3))
+
+
+@pytest.fixture(scope="module")
+def oracle_inputs():
+    job = _pd_job()
+    ref = O.compute_full(job)
+    assert ref["status"] == 0
+    B, eri = O.ri_assemble(ref["abP"], ref["PQ_chol"])
+    return job, ref, B, eri
+
+
+def test_ri_matches_oracle_on_oracle_inputs(ctx, oracle_inputs):
+    """Same (ab|P) and L on both sides (the oracle's): B and eri agree to rounding (relative 1e-11;
+    the solve amplifies rounding by at most the factor's condition number, about 1e2 here)."""
+    job, ref, Bo, erio = oracle_inputs
+    B, eri, ms = ctx.ri_assemble(ref["abP"], ref["PQ_chol"])
+    nb = len(job.basis)
+    assert B.shape == (75, nb * (nb + 1) // 2) and eri.shape == (B.shape[1], B.shape[1])
+    eb = np.max(np.abs(B - Bo)) / np.max(np.abs(Bo))
+    ee = np.max(np.abs(eri - erio)) / np.max(np.abs(erio))
+    _say(f"ri: B rel err {eb:.2e}, eri rel err {ee:.2e}, {ms:.3f} ms")
+    assert eb < 1e-11 and ee < 1e-11
+    assert np.array_equal(eri, eri.T)
+
+
+def test_ri_device_path_equals_host_path(ctx, oracle_inputs):
+    import torch
+    job, ref, _, _ = oracle_inputs
+    Bh, eh, _ = ctx.ri_assemble(ref["abP"], ref["PQ_chol"])
+    dev = torch.device("cuda:0")
+    Bd, ed, _ = ctx.ri_assemble(torch.from_numpy(ref["abP"]).to(dev), torch.from_numpy(ref["PQ_chol"]).to(dev))
+    assert np.array_equal(Bd.cpu().numpy(), Bh) and np.array_equal(ed.cpu().numpy(), eh)
+    # only one of the outputs
+    _, e2, _ = ctx.ri_assemble(ref["abP"], ref["PQ_chol"], want_B=False)
+    assert np.array_equal(e2, eh)
+    B3, e3, _ = ctx.ri_assemble(ref["abP"], ref["PQ_chol"], want_eri=False)
+    assert e3 is None and np.array_equal(B3, Bh)
+
+
+def test_ri_end_to_end_closed_forms(ctx):
+    """GPU quadrature + GPU Cholesky + GPU RI on 1s(zeta = 1) atoms with 1s(2) auxiliaries: the
+    densities lie in the auxiliary span, so (aa|aa) = 5/8 and (aa|bb) = J(R) exactly (up to the grid)."""
+    R = 1.4
+    job = MiniJob([[0.0, 0.0, 0.0], [0.0, 0.0, R]], [1.0, 1.0], [[0, 1, 0, 0, 1.0], [1, 1, 0, 0, 1.0]],
+                  [[0, 1, 0, 0, 2.0], [1, 1, 0, 0, 2.0]], Spec(30, 30, 10, 4, 3))
+    out, _, rc = ctx.compute(job)
+    assert rc == psint.PS_OK
+    _, eri, _ = ctx.ri_assemble(out["abP"], out["PQ_chol"])
+    J = 1 / R - math.exp(-2 * R) * (1 / R + 11 / 8 + 3 * R / 4 + R * R / 6)
+    aa, bb = O.pair_index(0, 0), O.pair_index(1, 1)
+    _say(f"(aa|aa) - 5/8 = {eri[aa, aa] - 0.625:.2e}, (aa|bb) - J = {eri[aa, bb] - J:.2e}")
+    assert abs(eri[aa, aa] - 0.625) < 1e-8 and abs(eri[bb, bb] - 0.625) < 1e-8
+    assert abs(eri[aa, bb] - J) < 1e-8
+
+
+@pytest.mark.parametrize("nb,na", [(1, 1), (2, 33), (11, 64), (12, 65)])
+def test_ri_edge_sizes(ctx, nb, na):
+    """Single pair / single auxiliary function, one-past-a-block sizes: random SPD factor and random
+    (ab|P) symmetric in a, b, compared with the oracle."""
+    rng = np.random.default_rng(nb * 100 + na)
+    M = rng.normal(size=(na, na))
+    L = np.linalg.cholesky(M @ M.T + na * np.eye(na))
+    abP = rng.normal(size=(na, nb, nb))
+    abP = 0.5 * (abP + abP.transpose(0, 2, 1))
+    Bo, eo = O.ri_assemble(abP, L)
+    B, e, _ = ctx.ri_assemble(abP, np.tril(L) + np.triu(rng.normal(size=(na, na)), 1))  # upper part ignored
+    assert np.max(np.abs(B - Bo)) <= 1e-12 * max(1.0, np.max(np.abs(Bo)))
+    assert np.max(np.abs(e - eo)) <= 1e-12 * max(1.0, np.max(np.abs(eo)))
+
+
+def test_ri_rejects_bad_arguments(ctx):
+    with pytest.raises(psint.PsError) as e:
+        ctx.ri_assemble(np.zeros((0, 3, 3)), np.zeros((0, 0)))
+    assert e.value.status == psint.PS_E_INVALID
