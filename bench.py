@@ -33,7 +33,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="triatomic_qz",
-                    choices=["triatomic_qz", "triatomic_5z", "diatomic_small", "hydrocarbon9", "serving_stream"])
+                    choices=["triatomic_qz", "triatomic_5z", "diatomic_small", "hydrocarbon9", "serving_stream",
+                             "grid_ladder", "nsp_sweep", "geometry_scan"])
     ap.add_argument("--autotune", action="store_true",
                     help="choose the contraction tiling with ps_autotune before the timed steps")
     ap.add_argument("--requests", type=int, default=40, help="serving_stream: measured requests")
@@ -87,6 +88,8 @@ def main():
 
     if args.workload == "serving_stream":
         return serve_bench(args, torch, psint, W)
+    if args.workload in ("grid_ladder", "nsp_sweep", "geometry_scan"):
+        return accuracy_bench(args, psint, W)
     job = W.WORKLOADS[args.workload]()
     prec = args.precision or job.precision
     ctx = psint.Context(0)
@@ -200,6 +203,36 @@ def ri_leg(ctx, outs, rc, psint, reps=3):
     t = float(np.mean(ms)) / 1e3
     return {"inputs": note, "n_pair": npair, "n_aux": na, "ms": t * 1e3, "flops": syrk + trsm,
             "achieved_tflops": (syrk + trsm) / t / 1e12, "frac_fp64_peak": (syrk + trsm) / t / PEAK["fp64"]}
+
+
+def accuracy_bench(args, psint, W):
+    """The grid-accuracy and geometry-scan harnesses at the paper's sizes: Table S3 ladders against
+    the 80 x 70 x 50-cell reference grid (eq. 13), N_SP = 1..4 on the OF2 shape and its stretched
+    variant, and the 16-direction two-centre Coulomb scan on the reference grid."""
+    from paper_2510_15204_amd import accuracy as A
+    ctx = psint.Context(0)
+    t0 = time.perf_counter()
+    if args.workload == "grid_ladder":
+        res = [A.grid_ladder(ctx, job, A.LADDER_S3) for job in (W.clf_tz(), W.of2_tz())]
+        body = {job["job"]: {"reference_points": job["reference_points"],
+                             "rows": [{"spec": r["spec"], "points": r["points"],
+                                       "rmse": {k: float(f"{v:.3e}") for k, v in r["rmse"].items()}}
+                                      for r in job["rows"]]} for job in res}
+    elif args.workload == "nsp_sweep":
+        res = [A.nsp_sweep(ctx, job, A.NSP_LADDER_S3) for job in (W.of2_tz(), W.of2_tz(long_bond=True))]
+        body = {r["job"]: {str(k): [float(f"{x:.3e}") for x in v] for k, v in r["rmse_V"].items()} for r in res}
+    else:
+        dist = [1.0 + 0.25 * i for i in range(21)]
+        scan = A.geometry_scan(ctx, dist)
+        fine_ok = {"jobs": scan["jobs"], "wall_s": scan["wall_s"], "pair_points": scan["pair_points"],
+                   "pairs": scan["pairs"], "distances": dist,
+                   "values_dir0": np.round(scan["values"][0], 10).tolist(),
+                   "values_dir15": np.round(scan["values"][15], 10).tolist()}
+        body = fine_ok
+    wall = time.perf_counter() - t0
+    print(json.dumps({"metric": f"{args.workload} (eq. 13 RMSE / Fig. 6 scan)", "value": wall, "unit": "s",
+                      "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": args.workload}, "result": body}), flush=True)
 
 
 def serve_bench(args, torch, psint, W):

@@ -55,7 +55,8 @@ SHELLS = {
 }
 
 # basis exponent ranges per element (lo, hi)
-ZETA_RANGE = {1: (0.4, 4.0), 6: (0.3, 10.0), 7: (0.3, 11.0), 8: (0.3, 12.0)}
+ZETA_RANGE = {1: (0.4, 4.0), 6: (0.3, 10.0), 7: (0.3, 11.0), 8: (0.3, 12.0), 9: (0.3, 13.0), 17: (0.25, 18.0)}
+BOHR_PER_ANGSTROM = 1.8897261246
 
 
 @dataclasses.dataclass
@@ -280,6 +281,32 @@ def serving_stream(n_requests=1100, rate_per_s=50.0, max_atoms=12, families=("DZ
         t += rng.exponential(1.0 / rate_per_s)
         out.append((t, random_molecule(rng, max_atoms, families, axis_points)))
     return out
+
+
+def clf_tz(spec=(26, 20, 8, 4, 3), seed_index=1) -> Job:
+    """ClF-shaped diatomic (bond 1.628 A) with triple-zeta-sized bases (25 + 25 functions, 75 + 75
+    auxiliary): the two-centre molecule of the paper's grid-convergence study (Figs. 3-4)."""
+    rng = rng_for(seed_index)
+    Z = np.array([17.0, 9.0])
+    xyz = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 1.628 * BOHR_PER_ANGSTROM]])
+    basis, aux = build_basis(rng, Z.astype(int), "TZ", "auxTZ", n_max=4)
+    return Job("ClF_TZ", xyz, Z, basis, aux, GridSpec(*spec))
+
+
+def of2_tz(spec=(26, 20, 8, 4, 3), long_bond=False, seed_index=1) -> Job:
+    """OF2-shaped triatomic (O-F 1.405 A, F-O-F 103.1 deg) with triple-zeta-sized bases: the
+    three-centre molecule of Figs. 3-5.  long_bond moves one F out to 41.41 A along its bond (the
+    stretched geometry of Fig. S1)."""
+    rng = rng_for(seed_index)
+    Z = np.array([8.0, 9.0, 9.0])
+    r = 1.405 * BOHR_PER_ANGSTROM
+    h = math.radians(103.1) / 2.0
+    u1 = np.array([math.sin(h), 0.0, math.cos(h)])
+    u2 = np.array([-math.sin(h), 0.0, math.cos(h)])
+    r1 = 41.41 * BOHR_PER_ANGSTROM if long_bond else r
+    xyz = np.array([[0.0, 0.0, 0.0], r1 * u1, r * u2])
+    basis, aux = build_basis(rng, Z.astype(int), "TZ", "auxTZ", n_max=4)
+    return Job("OF2_TZ_long" if long_bond else "OF2_TZ", xyz, Z, basis, aux, GridSpec(*spec))
 
 
 WORKLOADS = {
