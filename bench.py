@@ -244,8 +244,8 @@ def serve_bench(args, torch, psint, W):
     reqs = W.serving_stream(n_requests=n_warm + n_meas, rate_per_s=args.rate)
     prec = args.precision or "mixed"
     ctx = psint.Context(0)
-    for i in range(n_warm):
-        ctx.compute(reqs[i][1], outputs=("S", "T", "V", "PQ", "abP"), precision=prec, device=True)
+    for i in range(n_warm):  # through the serving path, so no synchronous arena stays allocated
+        ctx.wait(ctx.submit(reqs[i][1], outputs=("S", "T", "V", "PQ", "abP"), precision=prec, device=True))
         print(f"[bench] warmup request {i + 1}/{n_warm} done", flush=True)
     torch.cuda.synchronize()
     meas = reqs[n_warm:]
@@ -257,7 +257,13 @@ def serve_bench(args, torch, psint, W):
     def waiter():
         for i in range(n_meas):
             ready.acquire()
-            _, st, rc = ctx.wait(handles[i])
+            if handles[i] is None:  # rejected at submission
+                continue
+            try:
+                _, st, rc = ctx.wait(handles[i])
+            except psint.PsError as e:
+                st, rc = None, e.status
+                print(f"[bench] request {i} failed: {e}", flush=True)
             done[i] = (time.perf_counter(), st, rc)
             handles[i] = None  # release the device outputs
             if (i + 1) % 10 == 0:
@@ -273,14 +279,21 @@ def serve_bench(args, torch, psint, W):
         if due > now:
             time.sleep(due - now)
         arrivals.append(due)
-        handles[i] = ctx.submit(job, outputs=("S", "T", "V", "PQ", "abP"), precision=prec, device=True)
+        try:
+            handles[i] = ctx.submit(job, outputs=("S", "T", "V", "PQ", "abP"), precision=prec, device=True)
+        except psint.PsError as e:
+            handles[i] = None
+            print(f"[bench] request {i} rejected: {e}", flush=True)
         ready.release()
     th.join()
     torch.cuda.synchronize()
-    t_end = max(d[0] for d in done)
+    ok = [(d, a) for d, a in zip(done, arrivals) if d is not None and d[1] is not None]
+    rejected = n_meas - len(ok)
+    t_end = max(d[0] for d, _ in ok)
     makespan = t_end - t0
-    lat = np.array([(d[0] - a) * 1e3 for d, a in zip(done, arrivals)])
-    pp = sum(d[1]["pair_points"] for d in done)
+    lat = np.array([(d[0] - a) * 1e3 for d, a in ok])
+    pp = sum(d[1]["pair_points"] for d, _ in ok)
+    done = [d for d, _ in ok]
     atoms = [job.n_atoms for _, job in meas]
     out = {"metric": "S/T/V/(ab|P) quadrature pair·points/s at stated error vs FP64; p99 job latency",
            "value": pp / makespan, "unit": "pair·points/s", "n_gpus": 1, "steps": n_meas,
@@ -295,7 +308,7 @@ def serve_bench(args, torch, psint, W):
            "serving": {"makespan_s": makespan, "capacity_requests_per_s": n_meas / makespan,
                        "offered_load": args.rate * makespan / n_meas,
                        "mean_queue_ms": float(np.mean([d[1]["queue_ms"] for d in done])),
-                       "not_pd": int(sum(d[2] == psint.PS_E_NOT_PD for d in done))}}
+                       "not_pd": int(sum(d[2] == psint.PS_E_NOT_PD for d in done)), "rejected": rejected}}
     print(json.dumps(out), flush=True)
 
 

@@ -130,8 +130,10 @@ int32_t ps_compute(ps_ctx* ctx, const ps_job* job, ps_job_stats* st);
 
 /* ---- serving -------------------------------------------------------------------------------- */
 /* Queue a job (inputs are copied before return; output buffers must stay valid until ps_wait
- * returns for the ticket).  Jobs are admitted as device memory frees up and run concurrently on
- * the device (continuous batching).  PS_E_NOMEM if the job can never fit the budget. */
+ * returns for the ticket).  Jobs are admitted in arrival order as device memory frees up and run
+ * concurrently on the device (continuous batching, up to four at once).  The serving slots and the
+ * arena ps_compute keeps on the context share the context's budget.  PS_E_NOMEM if the job can
+ * never fit the budget.  One thread may submit while another waits. */
 int32_t ps_submit(ps_ctx* ctx, const ps_job* job, uint64_t* ticket);
 /* Wait for a ticket (timeout_us < 0: forever).  Returns the job's own status, or PS_E_TIMEOUT. */
 int32_t ps_wait(ps_ctx* ctx, uint64_t ticket, int64_t timeout_us, ps_job_stats* st);

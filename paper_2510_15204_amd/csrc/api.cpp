@@ -96,8 +96,8 @@ void compute_layout(const Plan& p, Layout& L) {
   L.items = take(L.items_host.size() * sizeof(int32_t));
   L.status = take(64);
   L.meta_end = o;
-  L.arrays = take(p.max_array_bytes);
-  L.ws = take(p.max_ws_bytes);
+  L.arrays = take(p.max_array_bytes);  // each pass: its arrays, then its partial tiles
+  L.ws = L.arrays;
   L.out = take((size_t)p.out_elems * sizeof(double));
   L.total = o;
 }
@@ -166,12 +166,12 @@ int32_t enqueue_job(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L) {
   const TileDev* tiles = (const TileDev*)(base + L.tiles);
   const RedDev* reds = (const RedDev*)(base + L.reds);
   const int32_t* items = (const int32_t*)(base + L.items);
-  double* ws = (double*)(base + L.ws);
   const bool mixed = p.precision == PS_PREC_MIXED;
   size_t item_pos = 0;
   s.n_contract = 0;
   for (size_t pi = 0; pi < p.passes.size(); ++pi) {
     const Pass& ps = p.passes[pi];
+    double* ws = (double*)(base + L.arrays + ps.ws_offset);
     HIP_TRY(launch_eval(mixed, segs + ps.seg0, ps.seg1 - ps.seg0, ps.eval_blocks, grids, lines,
                         (const ShellDev*)(base + L.shells), (const MEntry*)(base + L.ments),
                         (const WColDev*)(base + L.wcols), st));

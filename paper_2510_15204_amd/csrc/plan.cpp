@@ -821,15 +821,54 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
   // ---- passes: group grids so that arrays + workspace fit the budget ----
   const TileShape& shape2 = p.tile2;
   const size_t es = p.elem_size;
+  // row tiles of a task: BM consecutive pairs, halved until their staged U + V columns fit
+  auto row_tiles = [&](const TaskHost& th, const TileShape& sh) {
+    const int BM = sh.bm(), MAXUV = sh.maxuv();
+    const int32_t* pr = p.ints.data() + th.pairs_off;
+    const int npairs = th.dev.npairs;
+    std::vector<std::pair<int, int>> rows;
+    for (int r0 = 0; r0 < npairs; r0 += BM) {
+      std::vector<std::pair<int, int>> stack = {{r0, std::min(BM, npairs - r0)}};
+      while (!stack.empty()) {
+        auto [a0, n] = stack.back();
+        stack.pop_back();
+        int umin = 1 << 30, umax = -1, vmin = 1 << 30, vmax = -1;
+        for (int r = a0; r < a0 + n; ++r) {
+          umin = std::min(umin, pr[2 * r]);
+          umax = std::max(umax, pr[2 * r]);
+          vmin = std::min(vmin, pr[2 * r + 1]);
+          vmax = std::max(vmax, pr[2 * r + 1]);
+        }
+        if ((umax - umin + 1) + (vmax - vmin + 1) <= MAXUV || n == 1) {
+          rows.push_back({a0, n});
+        } else {
+          int h = n / 2;
+          stack.push_back({a0 + h, n - h});
+          stack.push_back({a0, h});
+        }
+      }
+    }
+    std::sort(rows.begin(), rows.end());
+    return rows;
+  };
+  auto shape_of = [&](const TaskHost& th) -> const TileShape& { return th.out_kind == 4 ? shape : shape2; };
+  // per grid: its arrays, and one partial tile per (row tile, column tile) item of its tasks
   std::vector<size_t> grid_bytes(p.grids.size(), 0);
-  for (auto& a : p.arrays) grid_bytes[a.grid] += (size_t)a.nf * p.grids[a.grid].dev.npad * es;
-  // reserve room for the partial tiles of a pass (about 2048 work-groups plus one per tile item) and
-  // the output buffer; the rest holds the arrays of the pass's grids
+  for (auto& a : p.arrays) grid_bytes[a.grid] += ((size_t)a.nf * p.grids[a.grid].dev.npad * es + 255) / 256 * 256;
+  for (auto& th : p.tasks) {
+    const TileShape& sh = shape_of(th);
+    const size_t items = row_tiles(th, sh).size() * (size_t)((th.dev.ny + sh.bn() - 1) / sh.bn());
+    grid_bytes[th.grid] += items * (size_t)sh.bm() * sh.bn() * 8;
+  }
+  // reserve the K-split workspace (about 2048 extra partial tiles per launch), the output buffer and
+  // the job's tables; the rest holds the arrays and per-item partial tiles of the pass's grids
   const size_t out_bytes = (size_t)p.out_elems * 8;
   const size_t ws_cap1 = std::min<size_t>((size_t)4096 * shape.bm() * shape.bn() * 8, budget / 4);
   const size_t ws_cap2 = std::min<size_t>((size_t)4096 * shape2.bm() * shape2.bn() * 8, budget / 16);
   const size_t ws_cap = ws_cap1 + ws_cap2;
-  size_t arr_budget = budget > ws_cap + out_bytes ? budget - ws_cap - out_bytes : 0;
+  // tables (grids, shells, tasks, tiles, pair lists): the pair lists plus a small allowance
+  const size_t tables = ((size_t)1 << 20) + budget / 256 + p.ints.size() * 4;
+  size_t arr_budget = budget > ws_cap + out_bytes + tables ? budget - ws_cap - out_bytes - tables : 0;
   {
     int g0 = 0;
     while (g0 < (int)p.grids.size()) {
@@ -863,7 +902,6 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       off = (off + 255) / 256 * 256;
     }
     ps.array_bytes = off;
-    p.max_array_bytes = std::max(p.max_array_bytes, off);
   }
   // segments: block offsets per pass
   {
@@ -899,34 +937,10 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
         TaskHost& th = p.tasks[t];
         const int grp = th.out_kind == 4 ? 0 : 1;
         const TileShape& sh = grp == 0 ? shape : shape2;
-        const int BM = sh.bm(), BN = sh.bn(), MAXUV = sh.maxuv();
+        const int BN = sh.bn();
         const int32_t* pr = p.ints.data() + th.pairs_off;
-        const int npairs = th.dev.npairs;
         const int64_t nch = p.grids[th.grid].dev.npad / KC;
-        // row tiles, halved until the staged columns fit
-        std::vector<std::pair<int, int>> rows;
-        for (int r0 = 0; r0 < npairs; r0 += BM) {
-          std::vector<std::pair<int, int>> stack = {{r0, std::min(BM, npairs - r0)}};
-          while (!stack.empty()) {
-            auto [a0, n] = stack.back();
-            stack.pop_back();
-            int umin = 1 << 30, umax = -1, vmin = 1 << 30, vmax = -1;
-            for (int r = a0; r < a0 + n; ++r) {
-              umin = std::min(umin, pr[2 * r]);
-              umax = std::max(umax, pr[2 * r]);
-              vmin = std::min(vmin, pr[2 * r + 1]);
-              vmax = std::max(vmax, pr[2 * r + 1]);
-            }
-            if ((umax - umin + 1) + (vmax - vmin + 1) <= MAXUV || n == 1) {
-              rows.push_back({a0, n});
-            } else {
-              int h = n / 2;
-              stack.push_back({a0 + h, n - h});
-              stack.push_back({a0, h});
-            }
-          }
-        }
-        std::sort(rows.begin(), rows.end());
+        const std::vector<std::pair<int, int>> rows = row_tiles(th, sh);
         for (auto& rw : rows) {
           int umin = 1 << 30, umax = -1, vmin = 1 << 30, vmax = -1;
           for (int r = rw.first; r < rw.first + rw.second; ++r) {
@@ -970,6 +984,8 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
           int64_t ns;
           if (p.ksplit_override > 0)
             ns = p.ksplit_override;
+          else if ((double)items[grp].size() >= ws_tiles)
+            ns = 1;  // the items alone fill the K-split allowance: one partial tile each
           else
             ns = (int64_t)std::llround(target * it.cost / std::max(total_cost[grp], 1.0));
           const int64_t nst = nch / TileShape::SC_MAX;  // whole stages (nch is a multiple of 16)
@@ -1012,6 +1028,9 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       }
       ps.tile1 = (int)p.tiles.size();
       ps.ws_elems = (size_t)ws;
+      // the pass's partial tiles follow its arrays in the shared region
+      ps.ws_offset = (ps.array_bytes + 255) / 256 * 256;
+      p.max_array_bytes = std::max(p.max_array_bytes, ps.ws_offset + (size_t)ws * 8);
       p.max_ws_bytes = std::max(p.max_ws_bytes, (size_t)ws * 8);
     }
   }

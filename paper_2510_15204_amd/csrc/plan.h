@@ -65,6 +65,7 @@ struct Pass {
   int64_t eval_blocks;
   size_t array_bytes;
   size_t ws_elems;
+  size_t ws_offset;     // bytes from the region start to the pass's partial tiles (after its arrays)
 };
 
 struct Plan {
@@ -98,7 +99,8 @@ struct Plan {
   double contract_flops = 0.0;
   double issued_flops = 0.0;
   int64_t n_points = 0;
-  size_t max_array_bytes = 0, max_ws_bytes = 0;
+  size_t max_array_bytes = 0;  // region per pass: arrays, then partial tiles (max over passes)
+  size_t max_ws_bytes = 0;     // partial tiles alone (max over passes)
   size_t meta_bytes = 0;
   size_t elem_size = 8;              // bytes per array element (8 FP64, 4 mixed)
 };

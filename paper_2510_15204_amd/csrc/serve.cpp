@@ -118,7 +118,8 @@ static void worker_loop(ps_ctx* ctx) {
     // admissions, in arrival order
     while (!S.queue.empty()) {
       auto t = S.queue.front();
-      size_t busy = 0;
+      // the synchronous slot's arena (ps_compute on this context) shares the budget
+      size_t busy = ctx->sync_slot.arena_size;
       int free_slot = -1;
       for (int si = 0; si < (int)S.slots.size(); ++si) {
         if (S.running[si]) busy += S.slots[si].arena_size;
