@@ -51,6 +51,20 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_hash():
+    """Hash of the sources that decide the contraction's memory traffic (kernels and tile planner)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_2510_15204_amd/csrc/kernels.hip", "paper_2510_15204_amd/csrc/plan.cpp"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def tiling_is_default(args, tuning):
+    return tuning is None and all(int(x) == 0 for x in args.tiling.split(","))
+
+
 def sample_elements(job, n_abp, rng):
     """Seeded sample of output elements of every kind (S, T, V, PQ, abP)."""
     nb, na = job.n_bf, job.n_aux
@@ -134,15 +148,17 @@ def main():
     achieved = flops / mean_contract_s
     traffic = None
     if os.path.exists(args.traffic_json):
+        # counters taken on this workload and precision with the current kernel and planner sources
         try:
             tj = json.load(open(args.traffic_json))
-            if tj.get("workload") == job.name and tj.get("precision") == prec:
+            if (tj.get("workload") == job.name and tj.get("precision") == prec
+                    and tj.get("source_hash") == kernel_source_hash() and tiling_is_default(args, tuning)):
                 traffic = tj.get("bytes_per_launch")
-        except Exception:
+        except (OSError, ValueError):
             traffic = None
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK[prec], "traffic": traffic,
-                "kernel": "contract_mixed" if prec == "mixed" else "contract_f64",
+                "kernel": ("contract_mixed" if prec == "mixed" else "contract_f64") + " (both launches)",
                 "flops_per_launch": flops, "mean_launch_ms": mean_contract_s * 1e3}
     out = {"metric": "S/T/V/(ab|P) quadrature pair·points/s at stated error vs FP64; p99 job latency",
            "value": value, "unit": "pair·points/s", "n_gpus": 1, "steps": args.steps,
