@@ -155,10 +155,14 @@ int32_t ps_eval_function(ps_ctx* ctx, int32_t what, const ps_sto* fn, const doub
 int32_t ps_plan_work(ps_ctx* ctx, const ps_job* job, double* pair_points, int64_t* n_grids,
                      int64_t* n_points, size_t* device_bytes);
 
-/* Contraction tile shape for later jobs on this context (0 = the built-in default for a field).
- * wm, wn in {2, 4}: 16x16 MFMA blocks per wave along the pair and column dimensions (a work-group
- * tile is 32*wm pairs x 32*wn columns); stage_chunks in {1, 2}: 16-point chunks per LDS stage;
- * ksplit: point-range splits per tile (0 = sized to fill the device).  PS_E_INVALID otherwise. */
+/* Contraction tile shape of the (ab|P) tiles for later jobs on this context.  wm, wn in {2, 4}: 16x16
+ * MFMA blocks per wave along the pair and column dimensions (a work-group tile is 32*wm pairs x
+ * 32*wn columns); stage_chunks in {1, 2}: 16-point chunks per LDS stage; ksplit: point-range splits
+ * per tile (0 = sized to fill the device).  wm = wn = stage_chunks = 0 restores the built-in default,
+ * which depends on each job's precision (FP64: 4, 4, 1; mixed: 4, 2, 2); a 0 among non-zero values
+ * takes the FP64 default for that field.  Two-index tiles (S, T, V, (P|Q)) always use 2, 2 with the
+ * same stage_chunks.  PS_E_INVALID otherwise.  ps_compute reuses the plan of the previous job on the
+ * context when the job's inputs, the tiling and the budget are unchanged. */
 int32_t ps_set_tiling(ps_ctx* ctx, int32_t wm, int32_t wn, int32_t stage_chunks, int32_t ksplit);
 
 /* ---- tile-shape autotuner ------------------------------------------------------------------- */

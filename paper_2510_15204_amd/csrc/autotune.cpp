@@ -54,10 +54,27 @@ extern "C" int32_t ps_autotune(ps_ctx* ctx, const ps_job* job, int32_t reps, ps_
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
   const TileShape saved = ctx->shape;
+  const bool saved_explicit = ctx->shape_explicit;
   const int saved_ksplit = ctx->ksplit;
+  ctx->shape_explicit = true;
   ps_tuning win{};
   win.device_ms = DBL_MAX;
   int n = 0;
+  {
+    // one untimed run first: module loading, first-touch of the arena and pinned staging
+    ctx->shape.wm = kCandidates[0][0];
+    ctx->shape.wn = kCandidates[0][1];
+    ctx->shape.sc = kCandidates[0][2];
+    ctx->ksplit = 0;
+    ps_tuning warm{};
+    int32_t rc = time_candidate(ctx, job, 1, &warm);
+    if (rc == PS_E_INVALID || rc == PS_E_UNSUPPORTED || rc == PS_E_DEVICE) {
+      ctx->shape = saved;
+      ctx->shape_explicit = saved_explicit;
+      ctx->ksplit = saved_ksplit;
+      return rc;
+    }
+  }
   int32_t first_err = PS_OK;
   std::string first_msg;
   for (const auto& c : kCandidates) {
@@ -74,6 +91,7 @@ extern "C" int32_t ps_autotune(ps_ctx* ctx, const ps_job* job, int32_t reps, ps_
     if (rc == PS_E_INVALID || rc == PS_E_UNSUPPORTED || rc == PS_E_DEVICE) {
       // the job itself is at fault (or the device is): no candidate can succeed
       ctx->shape = saved;
+      ctx->shape_explicit = saved_explicit;
       ctx->ksplit = saved_ksplit;
       return rc;
     }
@@ -91,6 +109,7 @@ extern "C" int32_t ps_autotune(ps_ctx* ctx, const ps_job* job, int32_t reps, ps_
   if (n_table) *n_table = n < max_table ? n : max_table;
   if (n == 0) {
     ctx->shape = saved;
+    ctx->shape_explicit = saved_explicit;
     ctx->ksplit = saved_ksplit;
     ctx->err = first_msg;
     return first_err;

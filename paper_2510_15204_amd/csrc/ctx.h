@@ -17,6 +17,15 @@
 
 namespace psint {
 
+// Device layout of one planned job: tables, then arrays, workspace and the FP64 output buffer.
+struct Layout {
+  size_t grids, lines, shells, ments, wcols, segs, tasks, tiles, reds, ints, items, status;
+  size_t meta_end;
+  size_t arrays, ws, out;
+  size_t total;
+  std::vector<int32_t> items_host;  // reduce item ids, concatenated per (pass, phase)
+};
+
 // Device resources of one in-flight job: stream, arena (tables + arrays + workspace + outputs),
 // pinned staging for its tables, and timing events.
 struct Slot {
@@ -30,6 +39,10 @@ struct Slot {
   std::vector<hipEvent_t> ev_contract;
   int n_contract = 0;
   bool want_chol = false;
+  // the plan last staged on this slot, reused when the same job comes again (ps_compute)
+  std::vector<char> plan_inputs;  // serialised job inputs + tiling + budget; empty = no valid plan
+  Plan plan;
+  Layout layout;
 };
 
 struct ServeState;
@@ -42,6 +55,7 @@ struct ps_ctx {
   hipStream_t user_stream = nullptr;
   std::string err;
   psint::TileShape shape;
+  bool shape_explicit = false;  // false: the default shape of the job's precision
   int ksplit = 0;
   psint::Slot sync_slot;
   psint::ServeState* serve = nullptr;  // created by the first ps_submit, freed by ps_destroy

@@ -7,16 +7,9 @@
 
 namespace psint {
 
-// Device layout of one planned job: tables, then arrays, workspace and the FP64 output buffer.
-struct Layout {
-  size_t grids, lines, shells, ments, wcols, segs, tasks, tiles, reds, ints, items, status;
-  size_t meta_end;
-  size_t arrays, ws, out;
-  size_t total;
-  std::vector<int32_t> items_host;  // reduce item ids, concatenated per (pass, phase)
-};
-
 void compute_layout(const Plan& p, Layout& L);
+// The contraction tile shape for a job: the context's explicit choice, else the precision's default.
+TileShape effective_shape(const ps_ctx* ctx, int32_t precision);
 // Plan the job and size its device layout (PS_E_NOMEM beyond the budget).
 int32_t plan_job(ps_ctx* ctx, const ps_job* job, Plan& plan, Layout& L);
 // Size the slot's arena and pinned staging (plus `extra_pinned` bytes) and stage the tables.

@@ -268,3 +268,31 @@ def test_autotune_selects_fastest_and_keeps_results():
     with pytest.raises(psint.PsError):
         c.autotune(job, reps=0)
     c.close()
+
+
+def test_plan_reuse_for_repeated_jobs():
+    """ps_compute keeps the last plan on the context: the same job again reuses it (identical
+    results), a changed job (one exponent, then the tiling) is planned afresh (results equal a fresh
+    context's)."""
+    job = _tri_tz((8, 8, 6, 4, 3, 2.3, 0.25))
+    c = psint.Context(0)
+    a1, _, _ = c.compute(job)
+    a2, _, _ = c.compute(job)
+    for k in psint.OUTPUTS:
+        assert np.array_equal(a1[k], a2[k]), k
+    changed = MiniJob(job.xyz, job.Z, job.basis.copy(), job.aux, job.grid)
+    changed.basis[3, 4] *= 1.1
+    b1, _, _ = c.compute(changed)
+    fresh = psint.Context(0)
+    b2, _, _ = fresh.compute(changed)
+    for k in psint.OUTPUTS:
+        assert np.array_equal(b1[k], b2[k]), k
+    assert not np.array_equal(a1["S"], b1["S"])
+    c.set_tiling(2, 2, 1, 0)
+    a3, _, _ = c.compute(job)
+    fresh.set_tiling(2, 2, 1, 0)
+    a4, _, _ = fresh.compute(job)
+    for k in psint.OUTPUTS:
+        assert np.array_equal(a3[k], a4[k]), k
+    c.close()
+    fresh.close()
