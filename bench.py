@@ -168,6 +168,7 @@ def main():
            "config": {"workload": job.name, "atoms": job.n_atoms, "n_bf": nb, "n_aux": na,
                       "grids": int(stats["n_grids"]), "points": int(stats["n_points"]),
                       "pair_points_per_step": pp, "precision": prec, "passes": int(stats["n_passes"]),
+                      "graph_replay": bool(stats["graph_replay"]),
                       "tiling": tuning["chosen"] if tuning else args.tiling},
            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
            "roofline": roofline}

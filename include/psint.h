@@ -111,6 +111,8 @@ typedef struct {
   double contract_flops; /* algorithmic FLOPs of the contraction kernels (2 per pair-point)      */
   double issued_flops;   /* FLOPs the contraction tiles issue, padding included                   */
   int64_t n_passes;      /* grid batches run one after another to fit the device-memory budget   */
+  int64_t graph_replay;  /* 1: the device work ran as a replay of a captured HIP graph (ps_compute of
+                            a job identical to the previous one on the context), else 0           */
 } ps_job_stats;
 
 typedef struct ps_ctx ps_ctx;

@@ -43,6 +43,9 @@ struct Slot {
   std::vector<char> plan_inputs;  // serialised job inputs + tiling + budget; empty = no valid plan
   Plan plan;
   Layout layout;
+  // device work of that plan captured once it repeats, replayed as one graph launch
+  hipGraphExec_t graph = nullptr;
+  bool graph_failed = false;       // capture not possible on this stream: stay with stream launches
 };
 
 struct ServeState;

@@ -62,7 +62,7 @@ class JobStats(C.Structure):
     _fields_ = [("n_grids", C.c_int64), ("n_points", C.c_int64), ("pair_points", C.c_double),
                 ("queue_ms", C.c_double), ("device_ms", C.c_double), ("total_ms", C.c_double),
                 ("contract_ms", C.c_double), ("contract_flops", C.c_double), ("issued_flops", C.c_double),
-                ("n_passes", C.c_int64)]
+                ("n_passes", C.c_int64), ("graph_replay", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -296,3 +296,28 @@ def test_plan_reuse_for_repeated_jobs():
         assert np.array_equal(a3[k], a4[k]), k
     c.close()
     fresh.close()
+
+
+def test_repeated_job_graph_replay_matches_eager():
+    """The second run of an unchanged job is captured into a HIP graph and later runs replay it: every
+    replay, with other device work in between, equals the first (eager) run bit for bit, and the
+    timing events inside the graph still report."""
+    import torch
+    job = _tri_tz((8, 8, 6, 4, 3, 2.3, 0.25))
+    c, other = psint.Context(0), psint.Context(0)
+    ref, st0, _ = c.compute(job)
+    x = torch.ones(1 << 20, dtype=torch.float64, device="cuda:0")
+    for i in range(5):
+        out, st, _ = c.compute(job)
+        for k in psint.OUTPUTS:
+            assert np.array_equal(out[k], ref[k]), (i, k)
+        assert st["contract_ms"] > 0 and st["device_ms"] >= st["contract_ms"]
+        assert st["graph_replay"] == 1 and st0["graph_replay"] == 0
+        other.compute(_serving_jobs()[i % 3])  # eager work on another context in between
+        x.mul_(1.0000001)
+        torch.cuda.synchronize()
+    dev, _, _ = c.compute(job, device=True)  # same plan, device outputs
+    for k in psint.OUTPUTS:
+        assert np.array_equal(dev[k].cpu().numpy(), ref[k]), k
+    c.close()
+    other.close()
