@@ -5,7 +5,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -22,6 +24,7 @@ hipError_t launch_contract_mixed(int wm, int wn, int sc, const TaskDev* tasks, c
                                  double* ws, hipStream_t st);
 hipError_t launch_reduce(const TaskDev* tasks, const RedDev* reds, const int32_t* items, int nitems,
                          const double* ws, hipStream_t st);
+int contract_resident_workgroups(bool mixed, int wm, int wn, int sc);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_symmetrize(double* X, int n, hipStream_t st);
 hipError_t launch_cholesky(const double* A, double* L, int n, int* status, hipStream_t st);
@@ -261,13 +264,27 @@ int32_t bind_slot(ps_ctx* ctx, Slot& s, const Plan& plan, const Layout& L, size_
 }
 
 TileShape effective_shape(const ps_ctx* ctx, int32_t precision) {
-  if (ctx && ctx->shape_explicit) return ctx->shape;
   TileShape t;  // FP64: 128 x 128 tiles, 16-point stages (two work-groups per CU)
-  if (precision == PS_PREC_MIXED) {
+  if (ctx && ctx->shape_explicit) {
+    t = ctx->shape;
+  } else if (precision == PS_PREC_MIXED) {
     // FP32 operands: 128 x 64 tiles with 32-point stages keep the FP64 accumulators and FP32
     // partial sums within two waves per SIMD (measured fastest on the triatomic 5Z and hydrocarbon)
     t.wn = 2;
     t.sc = 2;
+  }
+  // resident work-groups of this shape on the context's device: the planner rounds the K splits
+  // to whole waves of them (host-only planning without a context leaves 0: no rounding)
+  t.slots = 0;
+  if (ctx) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, int>, int> cache;
+    const auto key = std::make_tuple(ctx->device, (int)(precision == PS_PREC_MIXED), t.wm, t.wn, t.sc);
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it == cache.end())
+      it = cache.emplace(key, contract_resident_workgroups(precision == PS_PREC_MIXED, t.wm, t.wn, t.sc)).first;
+    t.slots = it->second;
   }
   return t;
 }

@@ -841,6 +841,29 @@ static hipError_t launch_contract_any(int wm, int wn, int sc, const TaskDev* tas
   return hipErrorInvalidValue;
 }
 
+// Work-groups of one contraction shape resident on the current device at once (occupancy x CUs),
+// 0 when the runtime cannot tell.
+template <typename T, int WM, int WN, int SC>
+static int resident_t() {
+  constexpr int lds = ContractCfg<T, WM, WN, SC>::LDS_BYTES;
+  const void* fn = sizeof(T) == 8 ? (const void*)contract_f64<WM, WN, SC> : (const void*)contract_mixed<WM, WN, SC>;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return 0;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds) != hipSuccess) return 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+int contract_resident_workgroups(bool mixed, int wm, int wn, int sc) {
+#define PS_SHAPE(a, b, c) \
+  if (wm == a && wn == b && sc == c) return mixed ? resident_t<float, a, b, c>() : resident_t<double, a, b, c>();
+  PS_SHAPE(4, 4, 1) PS_SHAPE(4, 4, 2) PS_SHAPE(2, 2, 1) PS_SHAPE(2, 2, 2)
+  PS_SHAPE(4, 2, 1) PS_SHAPE(4, 2, 2) PS_SHAPE(2, 4, 1) PS_SHAPE(2, 4, 2)
+#undef PS_SHAPE
+  return 0;
+}
+
 hipError_t launch_contract_f64(int wm, int wn, int sc, const TaskDev* tasks, const TileDev* tiles, int ntiles,
                                double* ws, hipStream_t st) {
   return launch_contract_any<double>(wm, wn, sc, tasks, tiles, ntiles, ws, st);

@@ -373,6 +373,7 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
   p.tile2 = shape;
   p.tile2.wm = 2;
   p.tile2.wn = 2;
+  p.tile2.slots = 0;
   p.ksplit_override = ksplit_override;
   p.atoms.assign(job->atoms, job->atoms + job->n_atoms);
   if (job->n_bf) p.basis.assign(job->basis, job->basis + job->n_bf);
@@ -992,18 +993,51 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
         const double ws_tiles = (double)(grp == 0 ? ws_cap1 : ws_cap2) / ((double)BM * BN * 8);
         const double target = std::max((double)items[grp].size(), std::min(2048.0, ws_tiles));
         const int tg0 = (int)p.tiles.size();
-        for (auto& it : items[grp]) {
-          TaskHost& th = p.tasks[it.task];
-          const int64_t nch = p.grids[th.grid].dev.npad / KC;
+        const size_t nit = items[grp].size();
+        std::vector<int64_t> nsv(nit), nstv(nit);
+        const bool fill_ws = (double)nit >= ws_tiles;
+        int64_t total_ns = 0;
+        for (size_t ii = 0; ii < nit; ++ii) {
+          const Item& it = items[grp][ii];
+          const int64_t nch = p.grids[p.tasks[it.task].grid].dev.npad / KC;
           int64_t ns;
           if (p.ksplit_override > 0)
             ns = p.ksplit_override;
-          else if ((double)items[grp].size() >= ws_tiles)
+          else if (fill_ws)
             ns = 1;  // the items alone fill the K-split allowance: one partial tile each
           else
             ns = (int64_t)std::llround(target * it.cost / std::max(total_cost[grp], 1.0));
           const int64_t nst = nch / TileShape::SC_MAX;  // whole stages (nch is a multiple of 16)
           ns = std::max<int64_t>(1, std::min<int64_t>(ns, std::max<int64_t>(1, nst / 8)));
+          nsv[ii] = ns;
+          nstv[ii] = nst;
+          total_ns += ns;
+        }
+        // round the launch up to whole waves of resident work-groups: split the items with the
+        // longest tiles once more until the last wave is full (its tiles would otherwise leave CUs
+        // idle while the launch drains)
+        if (sh.slots > 0 && p.ksplit_override <= 0 && !fill_ws && total_ns > 0) {
+          const int64_t want = (total_ns + sh.slots - 1) / sh.slots * sh.slots;
+          while (total_ns < want) {
+            int64_t best = -1;
+            double best_len = 0.0;
+            for (size_t ii = 0; ii < nit; ++ii) {
+              if (nsv[ii] >= std::max<int64_t>(1, nstv[ii] / 8)) continue;
+              const double len = (double)nstv[ii] / (double)nsv[ii];
+              if (len > best_len) {
+                best_len = len;
+                best = (int64_t)ii;
+              }
+            }
+            if (best < 0) break;
+            ++nsv[best];
+            ++total_ns;
+          }
+        }
+        for (size_t ii = 0; ii < nit; ++ii) {
+          const Item& it = items[grp][ii];
+          TaskHost& th = p.tasks[it.task];
+          const int64_t ns = nsv[ii], nst = nstv[ii];
           RedDev rd;
           rd.task = it.task;
           rd.row0 = it.row0;

@@ -16,6 +16,8 @@ namespace psint {
 struct TileShape {
   int wm = 4, wn = 4;
   int sc = 1;                             // storage chunks (16 points each) per contraction stage
+  int slots = 0;                          // work-groups of this shape resident on the device at once
+                                          // (0 = unknown: no rounding of the K splits)
   int bm() const { return 32 * wm; }
   int bn() const { return 32 * wn; }
   int maxuv() const { return bm() + 4; }  // staged U + V columns per tile
