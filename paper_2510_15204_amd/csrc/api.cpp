@@ -275,16 +275,20 @@ TileShape effective_shape(const ps_ctx* ctx, int32_t precision) {
   }
   // resident work-groups of this shape on the context's device: the planner rounds the K splits
   // to whole waves of them (host-only planning without a context leaves 0: no rounding)
-  t.slots = 0;
+  t.slots = t.slots2 = 0;
   if (ctx) {
     static std::mutex mu;
     static std::map<std::tuple<int, int, int, int, int>, int> cache;
-    const auto key = std::make_tuple(ctx->device, (int)(precision == PS_PREC_MIXED), t.wm, t.wn, t.sc);
+    const bool mixed = precision == PS_PREC_MIXED;
+    auto resident = [&](int wm, int wn, int sc) {
+      const auto key = std::make_tuple(ctx->device, (int)mixed, wm, wn, sc);
+      auto it = cache.find(key);
+      if (it == cache.end()) it = cache.emplace(key, contract_resident_workgroups(mixed, wm, wn, sc)).first;
+      return it->second;
+    };
     std::lock_guard<std::mutex> g(mu);
-    auto it = cache.find(key);
-    if (it == cache.end())
-      it = cache.emplace(key, contract_resident_workgroups(precision == PS_PREC_MIXED, t.wm, t.wn, t.sc)).first;
-    t.slots = it->second;
+    t.slots = resident(t.wm, t.wn, t.sc);
+    t.slots2 = resident(2, 2, t.sc);
   }
   return t;
 }

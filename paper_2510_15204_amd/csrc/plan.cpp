@@ -373,7 +373,7 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
   p.tile2 = shape;
   p.tile2.wm = 2;
   p.tile2.wn = 2;
-  p.tile2.slots = 0;
+  p.tile2.slots = shape.slots2;
   p.ksplit_override = ksplit_override;
   p.atoms.assign(job->atoms, job->atoms + job->n_atoms);
   if (job->n_bf) p.basis.assign(job->basis, job->basis + job->n_bf);
@@ -531,12 +531,14 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
     // arrays
     int aBA = add_array(gi, nA, std::vector<int32_t>(bA.begin(), bA.end()));
     int aBB = add_array(gi, nB, std::vector<int32_t>(bB.begin(), bB.end()));
-    int aKA = -1, aKB = -1, aXA = -1, aXB = -1;
+    int aKA = -1, aKB = -1, aXAB = -1;
     if (pg) {
       aKA = add_array(gi, nA, std::vector<int32_t>(bA.begin(), bA.end()));
       aKB = add_array(gi, nB, std::vector<int32_t>(bB.begin(), bB.end()));
-      aXA = add_array(gi, (int)ax_of[A].size(), std::vector<int32_t>(ax_of[A].begin(), ax_of[A].end()));
-      aXB = add_array(gi, (int)ax_of[B].size(), std::vector<int32_t>(ax_of[B].begin(), ax_of[B].end()));
+      // values of the auxiliary functions of A and B, one array [aux of A | aux of B]
+      std::vector<int32_t> xm(ax_of[A].begin(), ax_of[A].end());
+      xm.insert(xm.end(), ax_of[B].begin(), ax_of[B].end());
+      aXAB = add_array(gi, (int)xm.size(), xm);
     }
     // potential columns: pair grid [aux A | aux B | aux C]; other grids [aux C]
     std::vector<int32_t> ymap;
@@ -586,8 +588,8 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
     if (pg) {
       add_shell_seg(gi, mode_basis, CEN_A, p.basis, bA, aBA, aKA, 0);
       add_shell_seg(gi, mode_basis, CEN_B, p.basis, bB, aBB, aKB, 0);
-      add_shell_seg(gi, EV_CHI, CEN_A, p.aux, ax_of[A], aXA, -1, 0);
-      add_shell_seg(gi, EV_CHI, CEN_B, p.aux, ax_of[B], aXB, -1, 0);
+      add_shell_seg(gi, EV_CHI, CEN_A, p.aux, ax_of[A], aXAB, -1, 0);
+      add_shell_seg(gi, EV_CHI, CEN_B, p.aux, ax_of[B], aXAB, -1, (int)ax_of[A].size());
       add_shell_seg(gi, EV_POT_W, CEN_A, p.aux, ax_of[A], aY, -1, yA0);
       add_shell_seg(gi, EV_POT_W, CEN_B, p.aux, ax_of[B], aY, -1, yB0);
     } else {
@@ -695,9 +697,8 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       ts.push_back(t);
     };
     std::vector<int32_t> mA = iota_map(bA), mB = iota_map(bB);
-    std::vector<int32_t> mxA = iota_map(ax_of[A]), mxB = iota_map(ax_of[B]);
     const int64_t dSV = p.off_V - p.off_S;
-    const double dA = nA, dB = nB, pA = (double)ax_of[A].size(), pB = (double)ax_of[B].size();
+    const double dA = nA, dB = nB;
     if (pg) {
       // S_AB and V_AB (rows: a x {w, w O_AB}); mirrored into the (B, A) block
       two_index(aBA, mA, {cw, cOAB}, {0, 1}, aBB, mB, 0, nB, p.off_S, dSV, NB, true,
@@ -705,31 +706,43 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       // T raw, both orders (symmetrised at the end)
       two_index(aBA, mA, {cw}, {0}, aKB, mB, 0, nB, p.off_T, 0, NB, false, {{1, A, B, -1}}, dA * dB);
       two_index(aBB, mB, {cw}, {0}, aKA, mA, 0, nA, p.off_T, 0, NB, false, {{1, B, A, -1}}, 0);
-      // (P|Q) raw, both orders: sum w V_P chi_Q
+      // (P|Q) raw[P][Q] = sum w V_P chi_Q over the blocks this grid carries (A x B and B x A always,
+      // A x A and B x B when it is that atom's one-centre grid), as at most two rectangles of
+      // rows (Y column of V_P, weight column "ones") x columns (aux values [A | B])
       {
-        // rows: P on A (Y columns yA0..), weight column "ones"; cols: chi_Q, Q on B
-        std::vector<int32_t> mapUy(p.arrays[aY].nf, 0);
-        for (int k = 0; k < nyA; ++k) mapUy[yA0 + k] = ymap[yA0 + k];
-        TaskSpec t;
-        t.U = aY; t.V = aW; t.Y = aXB;
-        for (int k = 0; k < nyA; ++k) { t.pairs.push_back(yA0 + k); t.pairs.push_back(cone); }
-        t.mapU = mapUy; t.mapV.assign(wc.size(), 0); t.mapY = mxB;
-        t.y0 = 0; t.ny = (int)mxB.size();
-        t.out_off = p.off_PQ; t.s1 = NA; t.s2 = 0; t.s3 = 1;
-        t.outm_off = -1; t.t1 = t.t2 = t.t3 = 0; t.alpha = 1.0; t.skip_diag = 0;
-        t.keys = {{3, A, B, -1}}; t.work_elems = pA * pB; t.kind = 3;
-        if (!t.pairs.empty() && t.ny > 0) ts.push_back(t);
-        std::vector<int32_t> mapUy2(p.arrays[aY].nf, 0);
-        for (int k = 0; k < nyB; ++k) mapUy2[yB0 + k] = ymap[yB0 + k];
-        TaskSpec t2;
-        t2.U = aY; t2.V = aW; t2.Y = aXA;
-        for (int k = 0; k < nyB; ++k) { t2.pairs.push_back(yB0 + k); t2.pairs.push_back(cone); }
-        t2.mapU = mapUy2; t2.mapV.assign(wc.size(), 0); t2.mapY = mxA;
-        t2.y0 = 0; t2.ny = (int)mxA.size();
-        t2.out_off = p.off_PQ; t2.s1 = NA; t2.s2 = 0; t2.s3 = 1;
-        t2.outm_off = -1; t2.t1 = t2.t2 = t2.t3 = 0; t2.alpha = 1.0; t2.skip_diag = 0;
-        t2.keys = {{3, B, A, -1}}; t2.work_elems = 0; t2.kind = 3;
-        if (!t2.pairs.empty() && t2.ny > 0) ts.push_back(t2);
+        const int pA = (int)ax_of[A].size(), pB = (int)ax_of[B].size();
+        auto pq_task = [&](int y_lo, int y_n, int x_lo, int x_n, std::vector<std::tuple<int, int, int, int>> keys,
+                           double work) {
+          if (y_n <= 0 || x_n <= 0) return;
+          TaskSpec t;
+          t.U = aY; t.V = aW; t.Y = aXAB;
+          std::vector<int32_t> mapUy(p.arrays[aY].nf, 0);
+          for (int k = 0; k < y_n; ++k) {
+            mapUy[y_lo + k] = ymap[y_lo + k];
+            t.pairs.push_back(y_lo + k);
+            t.pairs.push_back(cone);
+          }
+          t.mapU = mapUy; t.mapV.assign(wc.size(), 0); t.mapY = p.arrays[aXAB].map;
+          t.y0 = x_lo; t.ny = x_n;
+          t.out_off = p.off_PQ; t.s1 = NA; t.s2 = 0; t.s3 = 1;
+          t.outm_off = -1; t.t1 = t.t2 = t.t3 = 0; t.alpha = 1.0; t.skip_diag = 0;
+          t.keys = keys; t.work_elems = work; t.kind = 3;
+          ts.push_back(t);
+        };
+        const double wAB = pA * pB, wAA = pA * (pA + 1) / 2.0, wBB = pB * (pB + 1) / 2.0;
+        const std::tuple<int, int, int, int> kAB{3, A, B, -1}, kBA{3, B, A, -1}, kAA{3, A, A, -1}, kBB{3, B, B, -1};
+        if (oneA && oneB) {
+          pq_task(yA0, nyA + nyB, 0, pA + pB, {kAB, kBA, kAA, kBB}, wAB + wAA + wBB);
+        } else if (oneA) {
+          pq_task(yA0, nyA + nyB, 0, pA, {kAA, kBA}, wAA);  // rows A and B x columns A
+          pq_task(yA0, nyA, pA, pB, {kAB}, wAB);            // rows A x columns B
+        } else if (oneB) {
+          pq_task(yA0, nyA + nyB, pA, pB, {kAB, kBB}, wAB + wBB);  // rows A and B x columns B
+          pq_task(yB0, nyB, 0, pA, {kBA}, 0.0);                      // rows B x columns A
+        } else {
+          pq_task(yA0, nyA, pA, pB, {kAB}, wAB);
+          pq_task(yB0, nyB, 0, pA, {kBA}, 0.0);
+        }
       }
       // (ab|P), a on A, b on B, P on A, B (and C*)
       abp_task(aBA, aBB, false, mA, mB, 0, p.arrays[aY].nf, true,
@@ -739,30 +752,17 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       for (int side = 0; side < 2; ++side) {
         const int X = side == 0 ? A : B, Yo = side == 0 ? B : A;
         const bool one = side == 0 ? oneA : oneB;
-        const int aBX = side == 0 ? aBA : aBB, aKX = side == 0 ? aKA : aKB, aXX = side == 0 ? aXA : aXB;
+        const int aBX = side == 0 ? aBA : aBB, aKX = side == 0 ? aKA : aKB;
         const std::vector<int32_t>& mX = side == 0 ? mA : mB;
-        const std::vector<int32_t>& mxX = side == 0 ? mxA : mxB;
         const int cO = side == 0 ? cOAA : cOBB;
-        const double n = mX.size(), pX = mxX.size();
+        const double n = mX.size();
         const double tri = n * (n + 1) / 2;
-        const int yX0 = side == 0 ? yA0 : yB0, nyX = side == 0 ? nyA : nyB;
         const int yO0 = side == 0 ? yB0 : yA0, nyO = side == 0 ? nyB : nyA;
         if (one) {
           two_index(aBX, mX, {cw, cO}, {0, 1}, aBX, mX, 0, (int)mX.size(), p.off_S, dSV, NB, false,
                     {{0, X, X, -1}, {2, X, X, -1}}, 2 * tri);
           two_index(aBX, mX, {cw}, {0}, aKX, mX, 0, (int)mX.size(), p.off_T, 0, NB, false,
                     {{1, X, X, -1}}, tri);
-          // (P|Q) raw on X
-          TaskSpec t;
-          t.U = aY; t.V = aW; t.Y = aXX;
-          std::vector<int32_t> mapUy(p.arrays[aY].nf, 0);
-          for (int k = 0; k < nyX; ++k) { mapUy[yX0 + k] = ymap[yX0 + k]; t.pairs.push_back(yX0 + k); t.pairs.push_back(cone); }
-          t.mapU = mapUy; t.mapV.assign(wc.size(), 0); t.mapY = mxX;
-          t.y0 = 0; t.ny = (int)mxX.size();
-          t.out_off = p.off_PQ; t.s1 = NA; t.s2 = 0; t.s3 = 1;
-          t.outm_off = -1; t.t1 = t.t2 = t.t3 = 0; t.alpha = 1.0; t.skip_diag = 0;
-          t.keys = {{3, X, X, -1}}; t.work_elems = pX * (pX + 1) / 2; t.kind = 3;
-          if (!t.pairs.empty() && t.ny > 0) ts.push_back(t);
           // (xx'|P), P on X and on the other focus: Y columns [A | B] are contiguous
           abp_task(aBX, aBX, true, mX, mX, 0, nyA + nyB, true, {{4, X, X, X}, {4, X, X, Yo}},
                    tri * (nyA + nyB));
@@ -771,7 +771,6 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
                     {{2, X, X, -1}}, tri);
           abp_task(aBX, aBX, true, mX, mX, yO0, nyO, true, {{4, X, X, Yo}}, tri * nyO);
         }
-        (void)pX;
       }
     } else {
       two_index(aBA, mA, {cOC}, {0}, aBB, mB, 0, nB, p.off_V, 0, NB, true, {{2, A, B, -1}, {2, B, A, -1}},

@@ -18,6 +18,7 @@ struct TileShape {
   int sc = 1;                             // storage chunks (16 points each) per contraction stage
   int slots = 0;                          // work-groups of this shape resident on the device at once
                                           // (0 = unknown: no rounding of the K splits)
+  int slots2 = 0;                         // the same for the 64 x 64 two-index shape
   int bm() const { return 32 * wm; }
   int bn() const { return 32 * wn; }
   int maxuv() const { return bm() + 4; }  // staged U + V columns per tile
