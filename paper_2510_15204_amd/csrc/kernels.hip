@@ -138,7 +138,7 @@ __constant__ double kFact[24] = {1.0,
 //   Gamma(k, x) = (k-1)! e^-x sum_{j<k} t_j,   gamma(k, x) = (k-1)! e^-x sum_{j>=k} t_j.
 // The lower one is the tail summed directly for x < k/2 (no cancellation; the terms fall at least
 // by half each step there), else (k-1)! (1 - e^-x head), whose relative rounding error 1e-16 / P(k, x)
-// stays below a few 1e-14 for x >= k/2 and k <= 15 (P the regularised lower gamma function).  The
+// stays below a few 1e-14 for x >= k/2 and k <= 20 (P the regularised lower gamma function).  The
 // earlier switch (x < k + 1 would also be safe) saves the long tails near x ~ k: 17% of evaluation.
 __device__ __forceinline__ void inc_gamma_pair(int k_lo, int k_up, double x, double ex, double* lower,
                                                double* upper) {
