@@ -550,7 +550,9 @@ __global__ __launch_bounds__(256, 1) void contract_mixed(const TaskDev* __restri
 }
 
 // Sum the splits of each reduction item in order and scatter into the FP64 output buffer.  Partial
-// tiles are row-major with R.bn columns; consecutive threads take consecutive columns.
+// tiles are row-major with R.bn columns.  Consecutive threads take consecutive pair rows: for (ab|P)
+// those are consecutive b, so the output writes are contiguous; the item's partial tiles (about 1 MB)
+// stay in L2 while the block strides through them.
 __global__ __launch_bounds__(256) void reduce_kernel(const TaskDev* __restrict__ tasks,
                                                      const RedDev* __restrict__ reds,
                                                      const int32_t* __restrict__ items,
@@ -558,11 +560,10 @@ __global__ __launch_bounds__(256) void reduce_kernel(const TaskDev* __restrict__
   const RedDev R = reds[items[blockIdx.x]];
   const TaskDev& T = tasks[R.task];
   const int64_t tile = (int64_t)R.bm * R.bn;
-  for (int e = threadIdx.x; e < R.nrows * R.bn; e += 256) {
-    const int row = e / R.bn, col = e - row * R.bn;
-    if (col >= R.np) continue;
+  for (int e = threadIdx.x; e < R.nrows * R.np; e += 256) {
+    const int col = e / R.nrows, row = e - col * R.nrows;
     double s = 0.0;
-    const double* p = ws + R.ws + e;
+    const double* p = ws + R.ws + (int64_t)row * R.bn + col;
     for (int k = 0; k < R.nsplit; ++k) s += p[k * tile];
     const int u = T.pairs[2 * (R.row0 + row)], v = T.pairs[2 * (R.row0 + row) + 1];
     const int y = T.y0 + R.p0 + col;
