@@ -186,16 +186,15 @@ int32_t enqueue_job(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L) {
       s.ev_contract.push_back(e1);
     }
     HIP_TRY(hipEventRecord(s.ev_contract[2 * pi], st));
-    // (ab|P) tiles, then the two-index tiles with their own shape
-    const int ranges[2][2] = {{ps.tile0, ps.tile_mid}, {ps.tile_mid, ps.tile1}};
-    for (int g = 0; g < 2; ++g) {
-      const TileShape& sh = g == 0 ? p.tile : p.tile2;
-      const int n = ranges[g][1] - ranges[g][0];
+    // one launch per tile shape: (ab|P) tiles, 64 x 64 tiles, narrow last-column tiles
+    for (const auto& lc : ps.launches) {
+      const int n = lc.tile1 - lc.tile0;
       if (n <= 0) continue;
+      const TileShape& sh = lc.shape;
       if (mixed)
-        HIP_TRY(launch_contract_mixed(sh.wm, sh.wn, sh.sc, tasks, tiles + ranges[g][0], n, ws, st));
+        HIP_TRY(launch_contract_mixed(sh.wm, sh.wn, sh.sc, tasks, tiles + lc.tile0, n, ws, st));
       else
-        HIP_TRY(launch_contract_f64(sh.wm, sh.wn, sh.sc, tasks, tiles + ranges[g][0], n, ws, st));
+        HIP_TRY(launch_contract_f64(sh.wm, sh.wn, sh.sc, tasks, tiles + lc.tile0, n, ws, st));
     }
     HIP_TRY(hipEventRecord(s.ev_contract[2 * pi + 1], st));
     s.n_contract++;

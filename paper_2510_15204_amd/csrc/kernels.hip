@@ -841,6 +841,8 @@ static hipError_t launch_contract_any(int wm, int wn, int sc, const TaskDev* tas
   if (wm == a && wn == b && sc == c) return launch_contract_t<T, a, b, c>(tasks, tiles, ntiles, ws, st);
   PS_SHAPE(4, 4, 1) PS_SHAPE(4, 4, 2) PS_SHAPE(2, 2, 1) PS_SHAPE(2, 2, 2)
   PS_SHAPE(4, 2, 1) PS_SHAPE(4, 2, 2) PS_SHAPE(2, 4, 1) PS_SHAPE(2, 4, 2)
+  PS_SHAPE(4, 1, 1) PS_SHAPE(4, 1, 2) PS_SHAPE(4, 3, 1) PS_SHAPE(4, 3, 2)
+  PS_SHAPE(2, 1, 1) PS_SHAPE(2, 1, 2) PS_SHAPE(2, 3, 1) PS_SHAPE(2, 3, 2)
 #undef PS_SHAPE
   return hipErrorInvalidValue;
 }
@@ -864,6 +866,8 @@ int contract_resident_workgroups(bool mixed, int wm, int wn, int sc) {
   if (wm == a && wn == b && sc == c) return mixed ? resident_t<float, a, b, c>() : resident_t<double, a, b, c>();
   PS_SHAPE(4, 4, 1) PS_SHAPE(4, 4, 2) PS_SHAPE(2, 2, 1) PS_SHAPE(2, 2, 2)
   PS_SHAPE(4, 2, 1) PS_SHAPE(4, 2, 2) PS_SHAPE(2, 4, 1) PS_SHAPE(2, 4, 2)
+  PS_SHAPE(4, 1, 1) PS_SHAPE(4, 1, 2) PS_SHAPE(4, 3, 1) PS_SHAPE(4, 3, 2)
+  PS_SHAPE(2, 1, 1) PS_SHAPE(2, 1, 2) PS_SHAPE(2, 3, 1) PS_SHAPE(2, 3, 2)
 #undef PS_SHAPE
   return 0;
 }

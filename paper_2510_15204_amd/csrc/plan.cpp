@@ -879,7 +879,8 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
   const size_t out_bytes = (size_t)p.out_elems * 8;
   const size_t ws_cap1 = std::min<size_t>((size_t)4096 * shape.bm() * shape.bn() * 8, budget / 4);
   const size_t ws_cap2 = std::min<size_t>((size_t)4096 * shape2.bm() * shape2.bn() * 8, budget / 16);
-  const size_t ws_cap = ws_cap1 + ws_cap2;
+  const size_t ws_cap3 = std::min<size_t>((size_t)4096 * shape.bm() * shape.bn() * 8, budget / 16);
+  const size_t ws_cap = ws_cap1 + ws_cap2 + ws_cap3;
   // tables (grids, shells, tasks, tiles, pair lists): the pair lists plus a small allowance
   const size_t tables = ((size_t)1 << 20) + budget / 256 + p.ints.size() * 4;
   size_t arr_budget = budget > ws_cap + out_bytes + tables ? budget - ws_cap - out_bytes - tables : 0;
@@ -945,12 +946,21 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
         int task, row0, nrows, p0, np, ulo, nu, vlo, nv;
         double cost;
       };
-      std::vector<Item> items[2];
-      double total_cost[2] = {0.0, 0.0};
+      // groups (one launch each): 0 the main shape, 1 the 64 x 64 shape, 2 + w for w = 1..3 the
+      // main shape narrowed to 32 w columns, which takes the last column tile of a main-shape task
+      // when that tile is at most 32 w wide (e.g. 345 columns = 128 + 128 + 96 instead of 3 x 128)
+      constexpr int NG = 5;
+      TileShape gshape[NG] = {shape, shape2, shape, shape, shape};
+      for (int w = 1; w <= 3; ++w) {
+        gshape[1 + w].wn = w;
+        gshape[1 + w].slots = 0;
+      }
+      std::vector<Item> items[NG];
+      double total_cost[NG] = {0.0, 0.0, 0.0, 0.0, 0.0};
       for (int t = ps.task0; t < ps.task1; ++t) {
         TaskHost& th = p.tasks[t];
-        const int grp = small_task[t] ? 1 : 0;
-        const TileShape& sh = grp == 0 ? shape : shape2;
+        const int grp0 = small_task[t] ? 1 : 0;
+        const TileShape& sh = gshape[grp0];
         const int BN = sh.bn();
         const int32_t* pr = p.ints.data() + th.pairs_off;
         const int64_t nch = p.grids[th.grid].dev.npad / KC;
@@ -975,6 +985,11 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
             it.vlo = vmin;
             it.nv = vmax - vmin + 1;
             it.cost = (double)nch;
+            int grp = grp0;
+            if (grp0 == 0) {
+              const int w = (it.np + 31) / 32;
+              if (w < shape.wn) grp = 1 + w;
+            }
             total_cost[grp] += it.cost;
             items[grp].push_back(it);
           }
@@ -982,14 +997,18 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       }
       int64_t ws = 0;
       ps.red_by_phase.clear();
+      ps.launches.clear();
       ps.tile0 = (int)p.tiles.size();
-      for (int grp = 0; grp < 2; ++grp) {
-        if (grp == 1) ps.tile_mid = (int)p.tiles.size();
-        const TileShape& sh = grp == 0 ? shape : shape2;
+      int n_narrow = 0;
+      for (int grp = 2; grp < NG; ++grp) n_narrow += items[grp].empty() ? 0 : 1;
+      for (int grp = 0; grp < NG; ++grp) {
+        if (items[grp].empty()) continue;
+        const TileShape& sh = gshape[grp];
         const int BM = sh.bm(), BN = sh.bn();
         // K splits: aim for about 8 work-groups per CU over 256 CUs per launch, within the group's
         // workspace reservation (one BM x BN FP64 partial tile per work-group)
-        const double ws_tiles = (double)(grp == 0 ? ws_cap1 : ws_cap2) / ((double)BM * BN * 8);
+        const size_t cap = grp == 0 ? ws_cap1 : (grp == 1 ? ws_cap2 : ws_cap3 / std::max(1, n_narrow));
+        const double ws_tiles = (double)cap / ((double)BM * BN * 8);
         const double target = std::max((double)items[grp].size(), std::min(2048.0, ws_tiles));
         const int tg0 = (int)p.tiles.size();
         const size_t nit = items[grp].size();
@@ -1072,6 +1091,7 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
           p.reds.push_back(rd);
         }
         xcd_order(p.tiles, tg0, (int)p.tiles.size());
+        ps.launches.push_back({tg0, (int)p.tiles.size(), sh});
       }
       ps.tile1 = (int)p.tiles.size();
       ps.ws_elems = (size_t)ws;

@@ -62,8 +62,12 @@ struct Pass {
   int grid0, grid1;     // grids [grid0, grid1)
   int seg0, seg1;       // segments
   int task0, task1;     // tasks
-  int tile0, tile1;     // tiles: [tile0, tile_mid) main shape, [tile_mid, tile1) the two-index shape
-  int tile_mid;
+  int tile0, tile1;     // all tiles of the pass
+  struct Launch {
+    int tile0, tile1;   // consecutive tiles of one contraction launch
+    TileShape shape;
+  };
+  std::vector<Launch> launches;  // main shape, 64 x 64 shape, then narrow last-column-tile shapes
   std::vector<std::vector<int>> red_by_phase;  // reduce item ids per phase
   int64_t eval_blocks;
   size_t array_bytes;
