@@ -949,14 +949,17 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       // groups (one launch each): 0 the main shape, 1 the 64 x 64 shape, 2 + w for w = 1..3 the
       // main shape narrowed to 32 w columns, which takes the last column tile of a main-shape task
       // when that tile is at most 32 w wide (e.g. 345 columns = 128 + 128 + 96 instead of 3 x 128)
-      constexpr int NG = 5;
-      TileShape gshape[NG] = {shape, shape2, shape, shape, shape};
+      // (group 5: the 64 x 64 shape narrowed to 32 columns, likewise for its tasks' last tiles)
+      constexpr int NG = 6;
+      TileShape gshape[NG] = {shape, shape2, shape, shape, shape, shape2};
       for (int w = 1; w <= 3; ++w) {
         gshape[1 + w].wn = w;
         gshape[1 + w].slots = 0;
       }
+      gshape[5].wn = 1;
+      gshape[5].slots = 0;
       std::vector<Item> items[NG];
-      double total_cost[NG] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      double total_cost[NG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       for (int t = ps.task0; t < ps.task1; ++t) {
         TaskHost& th = p.tasks[t];
         const int grp0 = small_task[t] ? 1 : 0;
@@ -986,10 +989,9 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
             it.nv = vmax - vmin + 1;
             it.cost = (double)nch;
             int grp = grp0;
-            if (grp0 == 0) {
-              const int w = (it.np + 31) / 32;
-              if (w < shape.wn) grp = 1 + w;
-            }
+            const int w = (it.np + 31) / 32;
+            if (grp0 == 0 && w < shape.wn) grp = 1 + w;
+            if (grp0 == 1 && w < shape2.wn) grp = 5;
             total_cost[grp] += it.cost;
             items[grp].push_back(it);
           }
@@ -1001,7 +1003,10 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       ps.tile0 = (int)p.tiles.size();
       int n_narrow = 0;
       for (int grp = 2; grp < NG; ++grp) n_narrow += items[grp].empty() ? 0 : 1;
-      for (int grp = 0; grp < NG; ++grp) {
+      // launch order: main, narrow main, 64 x 64, narrow 64 x 64
+      const int order[NG] = {0, 2, 3, 4, 1, 5};
+      for (int oi = 0; oi < NG; ++oi) {
+        const int grp = order[oi];
         if (items[grp].empty()) continue;
         const TileShape& sh = gshape[grp];
         const int BM = sh.bm(), BN = sh.bn();
