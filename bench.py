@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--rate", type=float, default=50.0, help="serving_stream: Poisson arrival rate, 1/s")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=15000, help="abP elements in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=45000, help="abP elements in the oracle sample")
     ap.add_argument("--tiling", default="0,0,0,0", help="wm,wn,stage_chunks,ksplit (0 = library default)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "contract_traffic.json"))
     ap.add_argument("--no-ri", action="store_true", help="skip the RI-assembly measurement after the steps")
@@ -162,7 +162,7 @@ def main():
             traffic = None
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK[prec], "traffic": traffic,
-                "kernel": ("contract_mixed" if prec == "mixed" else "contract_f64") + " (both launches)",
+                "kernel": ("contract_mixed" if prec == "mixed" else "contract_f64") + " (all launches)",
                 "flops_per_launch": flops, "mean_launch_ms": mean_contract_s * 1e3}
     out = {"metric": "S/T/V/(ab|P) quadrature pair·points/s at stated error vs FP64; p99 job latency",
            "value": value, "unit": "pair·points/s", "n_gpus": 1, "steps": args.steps,
