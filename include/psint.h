@@ -161,7 +161,7 @@ int32_t ps_plan_work(ps_ctx* ctx, const ps_job* job, double* pair_points, int64_
  * MFMA blocks per wave along the pair and column dimensions (a work-group tile is 32*wm pairs x
  * 32*wn columns); stage_chunks in {1, 2}: 16-point chunks per LDS stage; ksplit: point-range splits
  * per tile (0 = sized to fill the device).  wm = wn = stage_chunks = 0 restores the built-in default,
- * which depends on each job's precision (FP64: 4, 4, 1; mixed: 4, 2, 2); a 0 among non-zero values
+ * which depends on each job's precision (FP64: 4, 4, 1; mixed: 4, 4, 2); a 0 among non-zero values
  * takes the FP64 default for that field.  Two-index tiles (S, T, V, (P|Q)) always use 2, 2 with the
  * same stage_chunks.  PS_E_INVALID otherwise.  ps_compute reuses the plan of the previous job on the
  * context when the job's inputs, the tiling and the budget are unchanged. */

@@ -267,9 +267,8 @@ TileShape effective_shape(const ps_ctx* ctx, int32_t precision) {
   if (ctx && ctx->shape_explicit) {
     t = ctx->shape;
   } else if (precision == PS_PREC_MIXED) {
-    // FP32 operands: 128 x 64 tiles with 32-point stages keep the FP64 accumulators and FP32
-    // partial sums within two waves per SIMD (measured fastest on the triatomic 5Z and hydrocarbon)
-    t.wn = 2;
+    // FP32 operands: 128 x 128 tiles with 32-point stages (the FP32 stage sums of one row block at a
+    // time beside the FP64 accumulators fit two waves per SIMD)
     t.sc = 2;
   }
   // resident work-groups of this shape on the context's device: the planner rounds the K splits

@@ -360,6 +360,9 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
   // in the first two; the FP32 steps are half as long, so they spread over all (measured best)
   constexpr int CSPREAD = (sizeof(T) == 8 && KSTEPS > 2) ? 2 : KSTEPS;
   constexpr bool F64 = sizeof(T) == 8;
+  // FP32 tiles of more than 8 blocks per wave: stage sums kept per row block (row-block-outer step
+  // order) rather than for the whole tile, which keeps a 4 x 4 tile within two waves per SIMD
+  constexpr bool ROWOUTER = !F64 && WM * WN > 8;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform, lets tests below be scalar
   const int wm = wave >> 1, wn = wave & 1;
@@ -459,6 +462,46 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
   auto run_stage = [&](int s) {
     const bool more = s + 1 < nstage;
     const __attribute__((address_space(3))) T* cur = lds + (s & 1) * BUF;
+    if constexpr (ROWOUTER) {
+      // FP32: one row block at a time over the stage's steps, so only WN blocks of FP32 stage sums
+      // are live; they go into the FP64 accumulators after the row block's last step.  The Y
+      // operands are read from LDS once per row block.
+      constexpr int NIT = WM * KSTEPS;
+      T ru[2], rv[2], ry[2][WN];
+      auto fetch1 = [&](int it, int slot) {
+        const int mb = it / KSTEPS, kk = it - mb * KSTEPS;
+        ru[slot] = cur[offU[mb] + 4 * kk];
+        rv[slot] = cur[offV[mb] + 4 * kk];
+#pragma unroll
+        for (int nb = 0; nb < WN; ++nb) ry[slot][nb] = cur[offY[nb] + 4 * kk];
+      };
+      fetch1(0, 0);
+      f4_t s32[WN];
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int mb = it / KSTEPS, kk = it - mb * KSTEPS, sl = it & 1;
+        if (it + 1 < NIT) fetch1(it + 1, sl ^ 1);
+        const T av = ru[sl] * rv[sl];
+#pragma unroll
+        for (int nb = 0; nb < WN; ++nb)
+          s32[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ry[sl][nb], kk == 0 ? f4_t{} : s32[nb], 0, 0, 0);
+        if (more) {
+#pragma unroll
+          for (int i = 0; i < NCUV + NCY; ++i)
+            if (i % NIT == it) copy(s + 1, i);
+        }
+        if (kk == KSTEPS - 1) {
+#pragma unroll
+          for (int nb = 0; nb < WN; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[mb][nb][r] += (double)s32[nb][r];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+      return;
+    }
     Acc a32[WM][WN];
     if constexpr (!F64) {
 #pragma unroll
