@@ -134,34 +134,43 @@ __constant__ double kFact[24] = {1.0,
                                  1124000727777607680000.0,
                                  25852016738884976640000.0};
 
+// 1/j for j = 1..255 (entry 0 unused): the series below and the harmonic recurrence multiply by
+// these instead of dividing (an FP64 division is a ten-instruction sequence; the index is uniform
+// across a wave, so each entry is a scalar load).
+struct InvTable {
+  double v[256];
+};
+constexpr InvTable make_inv_table() {
+  InvTable t{};
+  t.v[0] = 0.0;
+  for (int j = 1; j < 256; ++j) t.v[j] = 1.0 / j;
+  return t;
+}
+__constant__ InvTable kInv = make_inv_table();
+
 // Integer-order incomplete gamma functions from the terms t_j = x^j / j!:
 //   Gamma(k, x) = (k-1)! e^-x sum_{j<k} t_j,   gamma(k, x) = (k-1)! e^-x sum_{j>=k} t_j.
 // The lower one is the tail summed directly for x < k/2 (no cancellation; the terms fall at least
 // by half each step there), else (k-1)! (1 - e^-x head), whose relative rounding error 1e-16 / P(k, x)
 // stays below a few 1e-14 for x >= k/2 and k <= 20 (P the regularised lower gamma function).  The
-// earlier switch (x < k + 1 would also be safe) saves the long tails near x ~ k: 17% of evaluation.
+// earlier switch (x < k + 1 would also be safe) saves the long tails near x ~ k.  Both head sums come
+// from one pass over the terms (k_up < k_lo).
 __device__ __forceinline__ void inc_gamma_pair(int k_lo, int k_up, double x, double ex, double* lower,
                                                double* upper) {
-  // upper: head sum to k_up - 1
-  double t = 1.0, head = 1.0;
-  for (int j = 1; j < k_up; ++j) {
-    t *= x / j;
-    head += t;
+  double t = 1.0, head = 1.0, h2 = 1.0;
+  for (int j = 1; j < k_lo; ++j) {
+    t *= x * kInv.v[j];
+    h2 += t;
+    if (j < k_up) head = h2;
   }
   *upper = kFact[k_up - 1] * ex * head;
-  // lower of order k_lo (> k_up)
-  double t2 = 1.0, h2 = 1.0;
-  for (int j = 1; j < k_lo; ++j) {
-    t2 *= x / j;
-    h2 += t2;
-  }
   if (x < 0.5 * k_lo) {
     double tail = 0.0;
-    double tj = t2 * x / k_lo;  // t_{k_lo}
+    double tj = t * x * kInv.v[k_lo];  // t_{k_lo}
     for (int j = k_lo; j < k_lo + 200; ++j) {
       tail += tj;
       if (tj < 1e-17 * tail) break;
-      tj *= x / (j + 1);
+      tj *= x * kInv.v[j + 1];
     }
     *lower = kFact[k_lo - 1] * ex * tail;
   } else {
@@ -260,7 +269,7 @@ __global__ __launch_bounds__(256) void eval_kernel(const SegDev* __restrict__ se
           cn = tl * z * Cm1[m];
           sn = tl * z * Sm1[m];
         } else if (m < l - 1) {
-          const double inv = 1.0 / (double)(l - m);
+          const double inv = kInv.v[l - m];
           cn = (tl * z * Cm1[m] - (l + m - 1.0) * Cm2[m]) * inv;
           sn = (tl * z * Sm1[m] - (l + m - 1.0) * Sm2[m]) * inv;
         }
@@ -452,12 +461,56 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
 #pragma unroll
     for (int nb = 0; nb < WN; ++nb) acc[mb][nb] = (d4_t){0.0, 0.0, 0.0, 0.0};
 
+  // Operand registers, two slots: the next step's operands are read from LDS while the current
+  // step's MFMAs run.  The first step of stage s + 1 is read right after the barrier that ends
+  // stage s.  In FP64 that barrier sits before the MFMAs of stage s's last step (whose operands are
+  // already in registers), so those MFMAs cover the LDS latency at the stage boundary; FP32 tiles
+  // keep it after the last step (holding the step's FP32 sums across it costs a wave per SIMD).
+  constexpr bool EARLY = F64;
+  T uA[2][WM], vA[2][WM], yB[2][WN];  // whole-tile step order
+  T ru[2], rv[2], ry[2][WN];          // row-block-outer step order
+  auto fetch = [&](const __attribute__((address_space(3))) T* cur, int kk, int slot) {
+#pragma unroll
+    for (int mb = 0; mb < WM; ++mb) {
+      uA[slot][mb] = cur[offU[mb] + 4 * kk];
+      vA[slot][mb] = cur[offV[mb] + 4 * kk];
+    }
+#pragma unroll
+    for (int nb = 0; nb < WN; ++nb) yB[slot][nb] = cur[offY[nb] + 4 * kk];
+  };
+  auto fetch1 = [&](const __attribute__((address_space(3))) T* cur, int it, int slot) {
+    const int mb = it / KSTEPS, kk = it - mb * KSTEPS;
+    ru[slot] = cur[offU[mb] + 4 * kk];
+    rv[slot] = cur[offV[mb] + 4 * kk];
+#pragma unroll
+    for (int nb = 0; nb < WN; ++nb) ry[slot][nb] = cur[offY[nb] + 4 * kk];
+  };
+  // FP64, before the last step's MFMAs of stage s (uniform): wait for this wave's copies of stage
+  // s + 1, barrier, then read the first operands of stage s + 1 into slot 0
+  auto boundary = [&](int s) {
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    fetch(lds + ((s + 1) & 1) * BUF, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  // FP32, after the stage's last step: the same wait and barrier; the next stage reads its first
+  // operands itself
+  auto stage_end = [&]() {
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  };
+
   if (nstage > 0) {
 #pragma unroll
     for (int i = 0; i < NCUV + NCY; ++i) copy(0, i);
   }
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
+  if constexpr (EARLY) {
+    if (nstage > 0) fetch(lds, 0, 0);
+  }
   // one stage: MFMAs on the current buffer, copies of the next stage into the other
   auto run_stage = [&](int s) {
     const bool more = s + 1 < nstage;
@@ -467,24 +520,19 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
       // are live; they go into the FP64 accumulators after the row block's last step.  The Y
       // operands are read from LDS once per row block.
       constexpr int NIT = WM * KSTEPS;
-      T ru[2], rv[2], ry[2][WN];
-      auto fetch1 = [&](int it, int slot) {
-        const int mb = it / KSTEPS, kk = it - mb * KSTEPS;
-        ru[slot] = cur[offU[mb] + 4 * kk];
-        rv[slot] = cur[offV[mb] + 4 * kk];
-#pragma unroll
-        for (int nb = 0; nb < WN; ++nb) ry[slot][nb] = cur[offY[nb] + 4 * kk];
-      };
-      fetch1(0, 0);
+      fetch1(cur, 0, 0);
       f4_t s32[WN];
 #pragma unroll
       for (int it = 0; it < NIT; ++it) {
         const int mb = it / KSTEPS, kk = it - mb * KSTEPS, sl = it & 1;
-        if (it + 1 < NIT) fetch1(it + 1, sl ^ 1);
+        if (it + 1 < NIT) fetch1(cur, it + 1, sl ^ 1);
         const T av = ru[sl] * rv[sl];
+        T bv[WN];
+#pragma unroll
+        for (int nb = 0; nb < WN; ++nb) bv[nb] = ry[sl][nb];
 #pragma unroll
         for (int nb = 0; nb < WN; ++nb)
-          s32[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ry[sl][nb], kk == 0 ? f4_t{} : s32[nb], 0, 0, 0);
+          s32[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[nb], kk == 0 ? f4_t{} : s32[nb], 0, 0, 0);
         if (more) {
 #pragma unroll
           for (int i = 0; i < NCUV + NCY; ++i)
@@ -497,11 +545,10 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
             for (int r = 0; r < 4; ++r) acc[mb][nb][r] += (double)s32[nb][r];
         }
       }
-      __builtin_amdgcn_sched_barrier(0);
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();
+      stage_end();
       return;
     }
+    if constexpr (!EARLY) fetch(cur, 0, 0);
     Acc a32[WM][WN];
     if constexpr (!F64) {
 #pragma unroll
@@ -509,27 +556,16 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
 #pragma unroll
         for (int nb = 0; nb < WN; ++nb) a32[mb][nb] = Acc{};
     }
-    // operands of step kk+1 are read from LDS while the MFMAs of step kk run
-    T uA[2][WM], vA[2][WM], yB[2][WN];
-    auto fetch = [&](int kk, int slot) {
-#pragma unroll
-      for (int mb = 0; mb < WM; ++mb) {
-        uA[slot][mb] = cur[offU[mb] + 4 * kk];
-        vA[slot][mb] = cur[offV[mb] + 4 * kk];
-      }
-#pragma unroll
-      for (int nb = 0; nb < WN; ++nb) yB[slot][nb] = cur[offY[nb] + 4 * kk];
-    };
-    fetch(0, 0);
 #pragma unroll
     for (int kk = 0; kk < KSTEPS; ++kk) {
       const int sl = kk & 1;
-      if (kk + 1 < KSTEPS) fetch(kk + 1, sl ^ 1);
+      if (kk + 1 < KSTEPS) fetch(cur, kk + 1, sl ^ 1);
       T av[WM], bv[WN];
 #pragma unroll
       for (int mb = 0; mb < WM; ++mb) av[mb] = uA[sl][mb] * vA[sl][mb];
 #pragma unroll
       for (int nb = 0; nb < WN; ++nb) bv[nb] = yB[sl][nb];
+      if (EARLY && kk + 1 == KSTEPS && more) boundary(s);
 #pragma unroll
       for (int mb = 0; mb < WM; ++mb)
 #pragma unroll
@@ -555,10 +591,7 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc[mb][nb][r] += (double)a32[mb][nb][r];
     }
-    // keep this stage's MFMAs ahead of the wait for the next stage's copies
-    __builtin_amdgcn_sched_barrier(0);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
+    if constexpr (!EARLY) stage_end();
   };
   for (int s = 0; s < nstage; ++s) run_stage(s);
   double* __restrict__ wt = ws + t.ws;
