@@ -616,8 +616,11 @@ __global__ __launch_bounds__(256, 1) void contract_f64(const TaskDev* __restrict
   contract_body<double, WM, WN, SC>(tasks[t.task], t, (__attribute__((address_space(3))) double*)smem_d, ws);
 }
 
+// Two waves per SIMD asked of the compiler: the widest FP32 tile then keeps its FP64 accumulators
+// and operands in VGPRs rather than splitting them into AGPRs (measured 2% faster than leaving the
+// allocation free).
 template <int WM, int WN, int SC>
-__global__ __launch_bounds__(256, 1) void contract_mixed(const TaskDev* __restrict__ tasks,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void contract_mixed(const TaskDev* __restrict__ tasks,
                                                          const TileDev* __restrict__ tiles,
                                                          double* __restrict__ ws) {
   extern __shared__ __attribute__((aligned(16))) float smem_f[];
