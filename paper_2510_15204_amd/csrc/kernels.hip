@@ -150,11 +150,11 @@ __constant__ InvTable kInv = make_inv_table();
 
 // Integer-order incomplete gamma functions from the terms t_j = x^j / j!:
 //   Gamma(k, x) = (k-1)! e^-x sum_{j<k} t_j,   gamma(k, x) = (k-1)! e^-x sum_{j>=k} t_j.
-// The lower one is the tail summed directly for x < k/2 (no cancellation; the terms fall at least
-// by half each step there), else (k-1)! (1 - e^-x head), whose relative rounding error 1e-16 / P(k, x)
-// stays below a few 1e-14 for x >= k/2 and k <= 20 (P the regularised lower gamma function).  The
-// earlier switch (x < k + 1 would also be safe) saves the long tails near x ~ k.  Both head sums come
-// from one pass over the terms (k_up < k_lo).
+// The lower one is (k-1)! (1 - e^-x head) unless the regularised P(k, x) = e^-x sum_{j>=k} t_j is
+// small, where that difference would cancel: its relative rounding error is about 1e-16 / P.  For
+// x < k/2 the tail terms fall at least by half each step, so e^-x t_k <= P <= 2 e^-x t_k; the tail is
+// summed directly when x < k/2 and e^-x t_k < 1e-3 (there its terms fall fast), else the complement
+// is used (relative error at most 3e-13 for k <= 24).  Both head sums come from one pass (k_up < k_lo).
 __device__ __forceinline__ void inc_gamma_pair(int k_lo, int k_up, double x, double ex, double* lower,
                                                double* upper) {
   double t = 1.0, head = 1.0, h2 = 1.0;
@@ -164,9 +164,9 @@ __device__ __forceinline__ void inc_gamma_pair(int k_lo, int k_up, double x, dou
     if (j < k_up) head = h2;
   }
   *upper = kFact[k_up - 1] * ex * head;
-  if (x < 0.5 * k_lo) {
-    double tail = 0.0;
-    double tj = t * x * kInv.v[k_lo];  // t_{k_lo}
+  const double tk = t * x * kInv.v[k_lo];  // t_{k_lo}
+  if (x < 0.5 * k_lo && ex * tk < 1e-3) {
+    double tail = 0.0, tj = tk;
     for (int j = k_lo; j < k_lo + 200; ++j) {
       tail += tj;
       if (tj < 1e-17 * tail) break;
@@ -201,20 +201,30 @@ __global__ __launch_bounds__(256) void eval_kernel(const SegDev* __restrict__ se
   }
   const SegDev& S = segs[lo];
   const GridDev& G = grids[S.grid];
-  const int64_t g = (b - S.block0) * 256 + threadIdx.x;
-  T* __restrict__ out0 = (T*)S.arr0;
-  T* __restrict__ out1 = (T*)S.arr1;
-  const int64_t base = (g / KC) * (int64_t)S.nf * KC + (g % KC);
+  // A wave's 64 points are 4 whole chunks of one grid (grids are padded to multiples of 256 points),
+  // so the output offset splits into a wave-uniform part (chunk g/16 starts at (g/16) * nf * 16 =
+  // gw * nf elements for the wave's first point gw, plus col * 16 for a column) and a fixed per-lane
+  // part below 4 * nf * 16: each store is a scalar base plus one 32-bit lane offset.
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = (b - S.block0) * 256 + __builtin_amdgcn_readfirstlane(threadIdx.x & ~63);
+  const int64_t g = gw + lane;
+  typedef __attribute__((address_space(1))) T GT;
+  GT* __restrict__ w0 = (GT*)S.arr0 + gw * S.nf;
+  GT* __restrict__ w1 = (GT*)S.arr1 + gw * S.nf;
+  const uint32_t loff = (uint32_t)((lane >> 4) * S.nf * KC + (lane & 15));
+  auto put0 = [&](int col, T v) { w0[(int64_t)col * KC + loff] = v; };
+  auto put1 = [&](int col, T v) { w1[(int64_t)col * KC + loff] = v; };
   if (g >= G.npts) {  // padding points: every column exactly zero
     if (S.mode == EV_WEIGHTS) {
-      for (int it = 0; it < S.n_items; ++it) out0[base + (int64_t)wcols[S.item_off + it].col * KC] = (T)0;
+      for (int it = 0; it < S.n_items; ++it) put0(wcols[S.item_off + it].col, (T)0);
     } else {
       for (int s = S.item_off; s < S.item_off + S.n_items; ++s) {
         const ShellDev sh = shells[s];
         for (int e = 0; e < sh.nm; ++e) {
-          const int64_t o = base + (int64_t)ments[sh.m_off + e].col * KC;
-          out0[o] = (T)0;
-          if (S.mode == EV_CHI_KIN) out1[o] = (T)0;
+          const int col = ments[sh.m_off + e].col;
+          if (col < 0) continue;
+          put0(col, (T)0);
+          if (S.mode == EV_CHI_KIN) put1(col, (T)0);
         }
       }
     }
@@ -233,7 +243,7 @@ __global__ __launch_bounds__(256) void eval_kernel(const SegDev* __restrict__ se
         if (W.zC != 0.0) pot += W.zC / geo.r[2];
         v = -geo.w * pot;
       }
-      out0[base + (int64_t)W.col * KC] = (T)v;
+      put0(W.col, (T)v);
     }
     return;
   }
@@ -296,17 +306,30 @@ __global__ __launch_bounds__(256) void eval_kernel(const SegDev* __restrict__ se
           kin = -0.5 * f * rad;
         }
       }
-      for (int e = 0; e < sh.nm; ++e) {
-        const MEntry me = ments[sh.m_off + e];
-        const int am = me.m < 0 ? -me.m : me.m;
-        double Yh = 0.0;
+      // components m = +mm (C) and -mm (S) for each |m| = mm <= l: the entries are dense in m, so
+      // the harmonic is a fixed register for each unrolled mm
+      // (all of the shell's entries are loaded before its first store)
+      const MEntry* __restrict__ me0 = ments + sh.m_off + l;  // m = 0
+      MEntry ep[LMAX + 1], en[LMAX + 1];
 #pragma unroll
-        for (int mm = 0; mm <= LMAX; ++mm)
-          if (mm == am) Yh = me.m < 0 ? Sv[mm] : C[mm];
-        Yh *= me.f;
-        const int64_t o = base + (int64_t)me.col * KC;
-        out0[o] = (T)(rad * Yh);
-        if (S.mode == EV_CHI_KIN) out1[o] = (T)(kin * Yh);
+      for (int mm = 0; mm <= LMAX; ++mm) {
+        if (mm > l) break;
+        ep[mm] = me0[mm];
+        en[mm] = me0[-mm];
+      }
+#pragma unroll
+      for (int mm = 0; mm <= LMAX; ++mm) {
+        if (mm > l) break;
+        if (ep[mm].col >= 0) {
+          const double Yh = C[mm] * ep[mm].f;
+          put0(ep[mm].col, (T)(rad * Yh));
+          if (S.mode == EV_CHI_KIN) put1(ep[mm].col, (T)(kin * Yh));
+        }
+        if (mm > 0 && en[mm].col >= 0) {
+          const double Yh = Sv[mm] * en[mm].f;
+          put0(en[mm].col, (T)(rad * Yh));
+          if (S.mode == EV_CHI_KIN) put1(en[mm].col, (T)(kin * Yh));
+        }
       }
     }
 #pragma unroll

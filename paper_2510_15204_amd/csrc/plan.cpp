@@ -84,7 +84,7 @@ double factorial(int n) {
 }
 
 // Shells of one atom's functions (caller order preserved in column order).  Functions sharing
-// (n, l, zeta) form one shell; each entry keeps its m and output column.
+// (n, l, zeta) form one shell, at most one function per m; each entry keeps its m and output column.
 struct ShellBuild {
   int n, l;
   double zeta;
@@ -97,7 +97,10 @@ std::vector<ShellBuild> make_shells(const std::vector<ps_sto>& fns, const std::v
     const ps_sto& f = fns[idx[c]];
     bool placed = false;
     for (auto& s : out) {
-      if (s.n == f.n && s.l == f.l && s.zeta == f.zeta) {
+      // one column per m in a shell (a repeated function starts another shell)
+      bool has_m = false;
+      for (auto& mc : s.ms) has_m = has_m || mc.first == f.m;
+      if (s.n == f.n && s.l == f.l && s.zeta == f.zeta && !has_m) {
         s.ms.push_back({f.m, c});
         placed = true;
         break;
@@ -486,15 +489,18 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       d.n = x.n;
       d.l = x.l;
       d.m_off = (int)p.ments.size();
-      d.nm = (int)x.ms.size();
+      d.nm = 2 * x.l + 1;
       d.pre = 4.0 * kPi / (2.0 * x.l + 1.0) * d.norm * std::pow(x.zeta, -(x.n + 1.0));
-      for (auto& mc : x.ms) {
+      // dense in m = -l..l (entry l + m); a component the basis does not hold has col -1
+      for (int m = -x.l; m <= x.l; ++m) {
         MEntry me;
-        int am = std::abs(mc.first);
+        const int am = std::abs(m);
         me.f = std::sqrt((2.0 * x.l + 1.0) / (4.0 * kPi) * factorial(x.l - am) / factorial(x.l + am)) *
                (am ? std::sqrt(2.0) : 1.0);
-        me.m = mc.first;
-        me.col = mc.second + col0;
+        me.m = m;
+        me.col = -1;
+        for (auto& mc : x.ms)
+          if (mc.first == m) me.col = mc.second + col0;
         p.ments.push_back(me);
       }
       p.shells.push_back(d);

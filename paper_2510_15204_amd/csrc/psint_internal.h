@@ -48,7 +48,8 @@ struct ShellDev {
 };
 
 // One m component of a shell: real-harmonic factor f (Y_lm = f * C_l^m or f * S_l^|m| of the unit
-// vector, see kernels.hip) and the output column.
+// vector, see kernels.hip) and the output column (-1: not in the basis).  A shell's entries are dense
+// in m = -l..l, entry m_off + l + m.
 struct MEntry {
   double f;
   int32_t m, col;
