@@ -652,9 +652,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
 }
 
 // Sum the splits of each reduction item in order and scatter into the FP64 output buffer.  Partial
-// tiles are row-major with R.bn columns.  Consecutive threads take consecutive pair rows: for (ab|P)
-// those are consecutive b, so the output writes are contiguous; the item's partial tiles (about 1 MB)
-// stay in L2 while the block strides through them.
+// tiles are row-major with R.bn columns (a multiple of 32, every entry written by the contraction).
+// A thread takes one pair row and 16 consecutive columns: per split it reads one whole 128-byte line
+// of the partial tile, so no line is fetched for a single value.  Consecutive threads take
+// consecutive pair rows: for (ab|P) those are consecutive b, so the output writes are contiguous.
 __global__ __launch_bounds__(256) void reduce_kernel(const TaskDev* __restrict__ tasks,
                                                      const RedDev* __restrict__ reds,
                                                      const int32_t* __restrict__ items,
@@ -662,17 +663,35 @@ __global__ __launch_bounds__(256) void reduce_kernel(const TaskDev* __restrict__
   const RedDev R = reds[items[blockIdx.x]];
   const TaskDev& T = tasks[R.task];
   const int64_t tile = (int64_t)R.bm * R.bn;
-  for (int e = threadIdx.x; e < R.nrows * R.np; e += 256) {
-    const int col = e / R.nrows, row = e - col * R.nrows;
-    double s = 0.0;
-    const double* p = ws + R.ws + (int64_t)row * R.bn + col;
-    for (int k = 0; k < R.nsplit; ++k) s += p[k * tile];
+  const int ngrp = (R.np + 15) / 16;
+  for (int e = threadIdx.x; e < R.nrows * ngrp; e += 256) {
+    const int cg = e / R.nrows, row = e - cg * R.nrows;
+    const int c0 = 16 * cg, nc = min(16, R.np - c0);
+    double sum[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) sum[c] = 0.0;
+    const double* p = ws + R.ws + (int64_t)row * R.bn + c0;
+    for (int k = 0; k < R.nsplit; ++k) {
+      const double2* q = (const double2*)(p + k * tile);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const double2 v = q[c];
+        sum[2 * c] += v.x;
+        sum[2 * c + 1] += v.y;
+      }
+    }
     const int u = T.pairs[2 * (R.row0 + row)], v = T.pairs[2 * (R.row0 + row) + 1];
-    const int y = T.y0 + R.p0 + col;
-    const int64_t ia = T.mapU[u], ib = T.mapV[v], ip = T.mapY[y];
-    const double val = T.alpha * s;
-    T.out[ia * T.s1 + ib * T.s2 + ip * T.s3] += val;
-    if (T.outm && !(T.skip_diag && ia == ib)) T.outm[ia * T.t1 + ib * T.t2 + ip * T.t3] += val;
+    const int64_t ia = T.mapU[u], ib = T.mapV[v];
+    const bool mirror = T.outm && !(T.skip_diag && ia == ib);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      if (c < nc) {
+        const int64_t ip = T.mapY[T.y0 + R.p0 + c0 + c];
+        const double val = T.alpha * sum[c];
+        T.out[ia * T.s1 + ib * T.s2 + ip * T.s3] += val;
+        if (mirror) T.outm[ia * T.t1 + ib * T.t2 + ip * T.t3] += val;
+      }
+    }
   }
 }
 
