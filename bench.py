@@ -55,12 +55,12 @@ def parse():
 
 def kernel_source_hash():
     """Hash of the sources that decide the contraction's memory traffic: the contraction kernels (the
-    part of kernels.hip from their section header to the reduction kernel) and the tile planner."""
+    part of kernels.hip from their section header to the reduction's) and the tile planner."""
     import hashlib
     h = hashlib.sha256()
     with open(os.path.join(ROOT, "paper_2510_15204_amd/csrc/kernels.hip"), encoding="utf-8") as fh:
         k = fh.read()
-    i, j = k.find("// Contraction kernels."), k.find("void reduce_kernel(")
+    i, j = k.find("// Contraction kernels."), k.find("// Sum the splits of each reduction item")
     h.update(k[i:j].encode() if 0 <= i < j else k.encode())
     with open(os.path.join(ROOT, "paper_2510_15204_amd/csrc/plan.cpp"), "rb") as fh:
         h.update(fh.read())
