@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--rate", type=float, default=50.0, help="serving_stream: Poisson arrival rate, 1/s")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=100000, help="abP elements in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=200000, help="abP elements in the oracle sample")
     ap.add_argument("--tiling", default="0,0,0,0", help="wm,wn,stage_chunks,ksplit (0 = library default)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "contract_traffic.json"))
     ap.add_argument("--no-ri", action="store_true", help="skip the RI-assembly measurement after the steps")
