@@ -7,6 +7,8 @@
 //                    registers from LDS-staged columns and fed to v_mfma_f64_16x16x4; each
 //                    work-group owns one (pair-rows x columns) tile over a range of point chunks and
 //                    writes an FP64 partial tile.
+//   contract_mixed   the same with FP32 operands and v_mfma_f32_16x16x4f32, each stage's FP32 sums
+//                    folded into FP64 accumulators.
 //   reduce_kernel    sums the partial tiles of a tile in split order (deterministic) and scatters
 //                    into the FP64 output buffer, with an optional mirrored write.
 //   symmetrize / cholesky / fill / copy helpers.
