@@ -61,16 +61,109 @@ int32_t ensure_pinned(ps_ctx* ctx, Slot& s, size_t bytes) {
   return PS_OK;
 }
 
+void* pool_alloc(ps_ctx* ctx, size_t bytes, size_t* got) {
+  constexpr size_t kGran = (size_t)2 << 20;
+  bytes = (bytes + kGran - 1) / kGran * kGran;
+  DevicePool& P = ctx->pool;
+  std::lock_guard<std::mutex> g(P.mu);
+  auto take = [&](DevicePool::Chunk& c) -> void* {
+    for (auto it = c.free.begin(); it != c.free.end(); ++it) {
+      if (it->second < bytes) continue;
+      const size_t off = it->first, len = it->second;
+      c.free.erase(it);
+      if (len > bytes) c.free[off + bytes] = len - bytes;
+      *got = bytes;
+      return c.base + off;
+    }
+    return nullptr;
+  };
+  for (auto& c : P.chunks)
+    if (void* p = take(c)) return p;
+  // a new chunk: a large request (a quarter of the budget or more) takes everything the budget has
+  // left, so that later arenas of any size fit without another allocation
+  auto add_chunk = [&](size_t size) -> void* {
+    DevicePool::Chunk c;
+    if (hipMalloc((void**)&c.base, size) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    c.size = size;
+    c.free[0] = size;
+    P.total += size;
+    P.chunks.push_back(c);
+    return take(P.chunks.back());
+  };
+  auto room = [&]() { return ctx->budget > P.total ? (ctx->budget - P.total) / kGran * kGran : (size_t)0; };
+  auto size_for = [&]() { return bytes >= ctx->budget / 4 ? std::max(bytes, room()) : bytes; };
+  if (bytes <= room())
+    if (void* p = add_chunk(size_for())) return p;
+  // give back chunks without ranges in use (their memory is cleared by the driver before reuse)
+  for (size_t i = 0; i < P.chunks.size();) {
+    auto& c = P.chunks[i];
+    if (c.free.size() == 1 && c.free.begin()->first == 0 && c.free.begin()->second == c.size) {
+      (void)hipFree(c.base);
+      P.total -= c.size;
+      P.chunks.erase(P.chunks.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+  if (bytes <= room()) return add_chunk(size_for());
+  return nullptr;
+}
+
+void pool_release(ps_ctx* ctx, void* p, size_t bytes) {
+  if (!p) return;
+  DevicePool& P = ctx->pool;
+  std::lock_guard<std::mutex> g(P.mu);
+  for (auto& c : P.chunks) {
+    if ((char*)p < c.base || (char*)p >= c.base + c.size) continue;
+    size_t off = (size_t)((char*)p - c.base), len = bytes;
+    auto next = c.free.lower_bound(off);
+    if (next != c.free.end() && next->first == off + len) {  // merge with the following range
+      len += next->second;
+      next = c.free.erase(next);
+    }
+    if (next != c.free.begin()) {  // merge with the preceding range
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        off = prev->first;
+        len += prev->second;
+        c.free.erase(prev);
+      }
+    }
+    c.free[off] = len;
+    return;
+  }
+}
+
+void pool_destroy(ps_ctx* ctx) {
+  DevicePool& P = ctx->pool;
+  std::lock_guard<std::mutex> g(P.mu);
+  for (auto& c : P.chunks) (void)hipFree(c.base);
+  P.chunks.clear();
+  P.total = 0;
+}
+
 int32_t ensure_arena(ps_ctx* ctx, Slot& s, size_t bytes) {
   if (s.arena_size >= bytes) return PS_OK;
   if (s.arena) {
     HIP_TRY(hipStreamSynchronize(s.stream));
-    (void)hipFree(s.arena);
+    pool_release(ctx, s.arena, s.arena_size);
   }
   s.arena = nullptr;
   s.arena_size = 0;
-  HIP_TRY(hipMalloc(&s.arena, bytes));
-  s.arena_size = bytes;
+  size_t got = 0;
+  void* p = pool_alloc(ctx, bytes, &got);
+  if (!p) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "no device memory for a %.2f GB arena within the %.2f GB budget", bytes / 1e9,
+             ctx->budget / 1e9);
+    ctx->err = buf;
+    return PS_E_NOMEM;
+  }
+  s.arena = p;
+  s.arena_size = got;
   return PS_OK;
 }
 
@@ -364,9 +457,9 @@ int32_t slot_init(ps_ctx* ctx, Slot& s, hipStream_t stream) {
   return PS_OK;
 }
 
-void slot_free(Slot& s) {
+void slot_free(ps_ctx* ctx, Slot& s) {
   if (s.stream) (void)hipStreamSynchronize(s.stream);
-  if (s.arena) (void)hipFree(s.arena);
+  if (s.arena) pool_release(ctx, s.arena, s.arena_size);
   if (s.pinned) (void)hipHostFree(s.pinned);
   drop_graph(s);
   for (auto e : s.ev_contract) (void)hipEventDestroy(e);
@@ -431,7 +524,8 @@ int32_t ps_destroy(ps_ctx* ctx) {
   if (!ctx) return PS_E_INVALID;
   serve_shutdown(ctx);
   (void)hipSetDevice(ctx->device);
-  slot_free(ctx->sync_slot);
+  slot_free(ctx, ctx->sync_slot);
+  pool_destroy(ctx);
   if (ctx->ri_buf) (void)hipFree(ctx->ri_buf);
   delete ctx;
   return PS_OK;

@@ -50,6 +50,22 @@ struct Slot {
 
 struct ServeState;
 
+// A context's device memory: chunks from hipMalloc kept until ps_destroy, handed out as ranges
+// (slot arenas).  Device memory that has been freed is cleared by the driver before it can be
+// mapped again, so a large hipFree followed by hipMalloc costs seconds (about 6 s for 160-200 GB
+// on MI355X); a range taken from a kept chunk costs nothing.  The sum of the chunks stays within
+// the context's budget.
+struct DevicePool {
+  struct Chunk {
+    char* base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free;  // offset -> length of the free ranges, coalesced
+  };
+  std::mutex mu;
+  std::vector<Chunk> chunks;
+  size_t total = 0;
+};
+
 }  // namespace psint
 
 struct ps_ctx {
@@ -64,13 +80,19 @@ struct ps_ctx {
   psint::ServeState* serve = nullptr;  // created by the first ps_submit, freed by ps_destroy
   void* ri_buf = nullptr;              // RI assembly scratch (grown on demand)
   size_t ri_buf_size = 0;
+  psint::DevicePool pool;              // slot arenas
 };
 
 namespace psint {
 
 struct Layout;
 int32_t slot_init(ps_ctx* ctx, Slot& s, hipStream_t stream);
-void slot_free(Slot& s);
+void slot_free(ps_ctx* ctx, Slot& s);
 void serve_shutdown(ps_ctx* ctx);
+// A range of at least `bytes` from the context's pool (nullptr: no room within the budget, even after
+// giving back chunks that hold no range).  Ranges are 2 MiB multiples; `*got` receives the size.
+void* pool_alloc(ps_ctx* ctx, size_t bytes, size_t* got);
+void pool_release(ps_ctx* ctx, void* p, size_t bytes);
+void pool_destroy(ps_ctx* ctx);
 
 }  // namespace psint

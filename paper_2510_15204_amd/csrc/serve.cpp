@@ -127,20 +127,31 @@ static void worker_loop(ps_ctx* ctx) {
       }
       if (free_slot < 0) break;
       if (busy + t->need_bytes > ctx->budget) break;  // wait for memory to free up
-      // release idle arenas that would push the total over the budget
-      size_t idle = 0;
-      for (int si = 0; si < (int)S.slots.size(); ++si)
-        if (!S.running[si] && si != free_slot) idle += S.slots[si].arena_size;
-      if (busy + idle + std::max(t->need_bytes, S.slots[free_slot].arena_size) > ctx->budget) {
-        for (int si = 0; si < (int)S.slots.size(); ++si)
-          if (!S.running[si] && si != free_slot && S.slots[si].arena) {
-            (void)hipFree(S.slots[si].arena);
-            S.slots[si].arena = nullptr;
-            S.slots[si].arena_size = 0;
-          }
+      // the job's arena: the free slot's own range if large enough, else a range from the context's
+      // pool, after giving back the ranges of idle slots if the pool has no room
+      Slot& s = S.slots[free_slot];
+      if (s.arena_size < t->need_bytes) {
+        pool_release(ctx, s.arena, s.arena_size);
+        s.arena = nullptr;
+        s.arena_size = 0;
+        size_t got = 0;
+        void* p = pool_alloc(ctx, t->need_bytes, &got);
+        if (!p) {
+          for (int si = 0; si < (int)S.slots.size(); ++si)
+            if (!S.running[si] && S.slots[si].arena) {
+              pool_release(ctx, S.slots[si].arena, S.slots[si].arena_size);
+              S.slots[si].arena = nullptr;
+              S.slots[si].arena_size = 0;
+            }
+          p = pool_alloc(ctx, t->need_bytes, &got);
+        }
+        bool any_running = false;
+        for (auto& r : S.running) any_running = any_running || (bool)r;
+        if (!p && any_running) break;  // wait for a running job to give its range back
+        s.arena = p;
+        s.arena_size = p ? got : 0;
       }
       S.queue.pop_front();
-      Slot& s = S.slots[free_slot];
       t->admitted = clk::now();
       t->slot = free_slot;
       const bool host_out = t->oj.job.out_location == PS_OUT_HOST;
@@ -177,7 +188,7 @@ static int32_t serve_start(ps_ctx* ctx) {
   for (auto& s : st->slots) {
     int32_t rc = slot_init(ctx, s, nullptr);
     if (rc) {
-      for (auto& s2 : st->slots) slot_free(s2);
+      for (auto& s2 : st->slots) slot_free(ctx, s2);
       delete st;
       return rc;
     }
@@ -195,7 +206,7 @@ void serve_shutdown(ps_ctx* ctx) {
   }
   ctx->serve->cv_work.notify_all();
   if (ctx->serve->worker.joinable()) ctx->serve->worker.join();
-  for (auto& s : ctx->serve->slots) slot_free(s);
+  for (auto& s : ctx->serve->slots) slot_free(ctx, s);
   delete ctx->serve;
   ctx->serve = nullptr;
 }
