@@ -121,7 +121,9 @@ typedef struct ps_ctx ps_ctx;
 /* Create a context on HIP device `hip_device` that keeps at most `hbm_budget_bytes` of device
  * memory for grids, function tables and workspaces (0 = 80% of the device's free memory).
  * `stream` is a hipStream_t to run on (NULL = the context creates its own).  Returns PS_OK and sets
- * *out, or a negative status.  The context owns all of its device memory. */
+ * *out, or a negative status.  The context owns all of its device memory: it is allocated as jobs
+ * need it (a job needing a quarter of the budget or more reserves the rest of the budget at once),
+ * reused by later jobs, and released by ps_destroy. */
 int32_t ps_create(int32_t hip_device, size_t hbm_budget_bytes, void* stream, ps_ctx** out);
 int32_t ps_destroy(ps_ctx* ctx);
 
