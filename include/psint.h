@@ -125,6 +125,8 @@ typedef struct ps_ctx ps_ctx;
  * need it (a job needing a quarter of the budget or more reserves the rest of the budget at once),
  * reused by later jobs, and released by ps_destroy. */
 int32_t ps_create(int32_t hip_device, size_t hbm_budget_bytes, void* stream, ps_ctx** out);
+/* Destroy a context: jobs already running on the device finish, submitted jobs not yet started are
+ * dropped, and all device memory of the context is released. */
 int32_t ps_destroy(ps_ctx* ctx);
 
 /* ---- synchronous compute -------------------------------------------------------------------- */

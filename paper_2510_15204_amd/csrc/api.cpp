@@ -95,8 +95,13 @@ void* pool_alloc(ps_ctx* ctx, size_t bytes, size_t* got) {
   };
   auto room = [&]() { return ctx->budget > P.total ? (ctx->budget - P.total) / kGran * kGran : (size_t)0; };
   auto size_for = [&]() { return bytes >= ctx->budget / 4 ? std::max(bytes, room()) : bytes; };
+  // (the larger chunk may not be there to take, e.g. held by another context: then the exact size)
+  auto add = [&]() -> void* {
+    void* p = add_chunk(size_for());
+    return p || size_for() == bytes ? p : add_chunk(bytes);
+  };
   if (bytes <= room())
-    if (void* p = add_chunk(size_for())) return p;
+    if (void* p = add()) return p;
   // give back chunks without ranges in use (their memory is cleared by the driver before reuse)
   for (size_t i = 0; i < P.chunks.size();) {
     auto& c = P.chunks[i];
@@ -108,7 +113,7 @@ void* pool_alloc(ps_ctx* ctx, size_t bytes, size_t* got) {
       ++i;
     }
   }
-  if (bytes <= room()) return add_chunk(size_for());
+  if (bytes <= room()) return add();
   return nullptr;
 }
 
@@ -587,6 +592,7 @@ static std::vector<char> plan_inputs(const ps_ctx* ctx, const ps_job* job) {
 
 int32_t ps_compute(ps_ctx* ctx, const ps_job* job, ps_job_stats* st) {
   if (!ctx || !job) return PS_E_INVALID;
+  std::lock_guard<std::mutex> sync_guard(ctx->sync_mu);
   auto t0 = std::chrono::steady_clock::now();
   if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
   Slot& s = ctx->sync_slot;

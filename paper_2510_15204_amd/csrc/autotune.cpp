@@ -53,6 +53,7 @@ extern "C" int32_t ps_autotune(ps_ctx* ctx, const ps_job* job, int32_t reps, ps_
     return PS_E_INVALID;
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
+  std::lock_guard<std::mutex> sync_guard(ctx->sync_mu);
   const TileShape saved = ctx->shape;
   const bool saved_explicit = ctx->shape_explicit;
   const int saved_ksplit = ctx->ksplit;

@@ -77,6 +77,8 @@ struct ps_ctx {
   bool shape_explicit = false;  // false: the default shape of the job's precision
   int ksplit = 0;
   psint::Slot sync_slot;
+  std::mutex sync_mu;  // held while ps_compute / ps_autotune use sync_slot; the serving dispatcher
+                       // takes an idle sync_slot's arena back when a queued job needs the memory
   psint::ServeState* serve = nullptr;  // created by the first ps_submit, freed by ps_destroy
   void* ri_buf = nullptr;              // RI assembly scratch (grown on demand)
   size_t ri_buf_size = 0;

@@ -27,6 +27,8 @@ int32_t finish_stats(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, ps_jo
                      double queue_ms);
 int32_t ensure_pinned(ps_ctx* ctx, Slot& s, size_t bytes);
 int32_t ensure_arena(ps_ctx* ctx, Slot& s, size_t bytes);
+// Destroy the slot's captured graph (its kernels refer to the slot's current arena and tables).
+void drop_graph(Slot& s);
 size_t output_bytes(const Plan& p, const ps_job& job);
 
 }  // namespace psint

@@ -126,9 +126,33 @@ static void worker_loop(ps_ctx* ctx) {
         else if (free_slot < 0 || S.slots[si].arena_size > S.slots[free_slot].arena_size) free_slot = si;
       }
       if (free_slot < 0) break;
+      // no ps_compute running: its slot's arena (kept for a repeat of its last job) goes back to
+      // the pool, with the plan and graph that refer to it; false if a ps_compute holds the slot
+      auto reclaim_sync = [&]() {
+        if (!ctx->sync_mu.try_lock()) return false;
+        Slot& ss = ctx->sync_slot;
+        if (ss.arena) {
+          (void)hipStreamSynchronize(ss.stream);
+          pool_release(ctx, ss.arena, ss.arena_size);
+          ss.arena = nullptr;
+          ss.arena_size = 0;
+          ss.plan_inputs.clear();
+          drop_graph(ss);
+        }
+        ctx->sync_mu.unlock();
+        return true;
+      };
+      bool sync_busy = false;
+      if (busy + t->need_bytes > ctx->budget && ctx->sync_slot.arena) {
+        sync_busy = !reclaim_sync();
+        busy = ctx->sync_slot.arena_size;
+        for (int si = 0; si < (int)S.slots.size(); ++si)
+          if (S.running[si]) busy += S.slots[si].arena_size;
+      }
       if (busy + t->need_bytes > ctx->budget) break;  // wait for memory to free up
       // the job's arena: the free slot's own range if large enough, else a range from the context's
-      // pool, after giving back the ranges of idle slots if the pool has no room
+      // pool, after giving back the ranges of idle slots (then of an idle ps_compute slot) if the
+      // pool has no room
       Slot& s = S.slots[free_slot];
       if (s.arena_size < t->need_bytes) {
         pool_release(ctx, s.arena, s.arena_size);
@@ -145,7 +169,11 @@ static void worker_loop(ps_ctx* ctx) {
             }
           p = pool_alloc(ctx, t->need_bytes, &got);
         }
-        bool any_running = false;
+        if (!p) {
+          sync_busy = !reclaim_sync();
+          p = pool_alloc(ctx, t->need_bytes, &got);
+        }
+        bool any_running = sync_busy;
         for (auto& r : S.running) any_running = any_running || (bool)r;
         if (!p && any_running) break;  // wait for a running job to give its range back
         s.arena = p;
@@ -172,9 +200,20 @@ static void worker_loop(ps_ctx* ctx) {
     bool busy = false;
     for (auto& r : S.running)
       if (r) busy = true;
+    if (S.stop && !S.queue.empty()) {
+      // ps_destroy: jobs not yet admitted are not started (running ones finish first)
+      for (auto& q : S.queue) {
+        q->status = PS_E_DEVICE;
+        q->done = true;
+      }
+      S.queue.clear();
+      S.cv_done.notify_all();
+    }
     if (S.stop && S.queue.empty() && !busy) break;
     if (busy)
       S.cv_work.wait_for(lk, std::chrono::microseconds(50));
+    else if (!S.queue.empty())  // waiting for a ps_compute on this context to finish
+      S.cv_work.wait_for(lk, std::chrono::microseconds(500));
     else
       S.cv_work.wait(lk, [&] { return S.stop || !S.queue.empty(); });
   }

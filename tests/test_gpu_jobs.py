@@ -242,6 +242,45 @@ def test_memory_passes_match_single_pass():
     big.close()
 
 
+def test_device_pool_reuse_across_job_sizes():
+    """One context runs jobs of growing and shrinking size (its arena ranges move within the device
+    pool; one job needs a quarter of the budget or more and reserves the rest of it; one needs two
+    grid passes) and each result is bit-identical to the same job on a fresh context."""
+    xyz = np.array([[0.0, 0.0, 0.0], [1.9, 0.2, 0.0], [-0.4, 1.8, 0.3], [0.6, -0.5, 2.0]])
+    basis = [[a, 1, 0, 0, 1.2 + 0.3 * a] for a in range(4)] + [[a, 2, 1, 1, 1.0] for a in range(4)]
+    aux = [[a, 1, 0, 0, 2.5] for a in range(4)] + [[a, 2, 1, -1, 2.0] for a in range(4)]
+    small = MiniJob(xyz[:2], [6, 1], basis[:1] + basis[4:5], aux[:1], Spec(6, 6, 4))
+    medium = MiniJob(xyz[:3], [6, 1, 8], [b for b in basis if b[0] < 3], [q for q in aux if q[0] < 3],
+                     Spec(8, 8, 6))
+    large = MiniJob(xyz, [6, 1, 8, 1], basis, aux, Spec(10, 10, 8, 4, 3))
+    probe = psint.Context(0)
+    need = probe.plan_work(large)["device_bytes"]
+    probe.close()
+    budget = int(need * 0.6)  # the large job alone needs two passes here; it takes over 1/4 of it
+    jobs = [("small", small), ("medium", medium), ("large", large), ("small", small), ("medium", medium)]
+    refs = {}
+    for name, job in jobs[:3]:
+        fresh = psint.Context(0, budget_bytes=budget)
+        refs[name], st, _ = fresh.compute(job)
+        fresh.close()
+        _say(f"{name}: {st['n_passes']} passes")
+    c = psint.Context(0, budget_bytes=budget)
+    for name, job in jobs:
+        got, st, _ = c.compute(job)
+        for k in psint.OUTPUTS:
+            assert np.array_equal(got[k], refs[name][k]), (name, k)
+        _say(f"compute {name} ok")
+    # the same through the serving path, all submitted at once (the idle arena of the synchronous
+    # path, sized for the large job, is taken back when the served large job needs the memory)
+    hs = [c.submit(job) for _, job in jobs]
+    for (name, _), h in zip(jobs, hs):
+        got, _, _ = c.wait(h, timeout_us=60_000_000)
+        for k in psint.OUTPUTS:
+            assert np.array_equal(got[k], refs[name][k]), (name, k, "served")
+        _say(f"served {name} ok")
+    c.close()
+
+
 def test_autotune_selects_fastest_and_keeps_results():
     """ps_autotune times every candidate tiling, leaves the fastest on the context, and a job run with
     it agrees with the default tiling (up to the summation order of the point splits) and the oracle."""
