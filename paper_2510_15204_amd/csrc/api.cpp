@@ -251,15 +251,16 @@ static void stage_meta(const Plan& p, const Layout& L, char* base, char* host) {
   std::memset(host + L.status, 0, 64);
 }
 
-// Enqueue every step of a planned job on slot s (no synchronisation).  Events bracket the device
-// work and the contraction launches.
-int32_t enqueue_job(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L) {
+// The device work of a planned job in segments: 0 = table copy, output clear and the evaluation of
+// pass 0; 2i + 1 = the contraction launches of pass i; 2i + 2 = the reductions of pass i, then the
+// evaluation of pass i + 1, or after the last pass the symmetrisation and the Cholesky factorisation.
+int num_segments(const Plan& p) { return 2 * (int)p.passes.size() + 1; }
+
+int32_t enqueue_segment(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, int k) {
+  (void)ctx;
   char* base = (char*)s.arena;
   hipStream_t st = s.stream;
-  HIP_TRY(hipEventRecord(s.ev_start, st));
-  HIP_TRY(hipMemcpyAsync(base, s.pinned, L.meta_end, hipMemcpyHostToDevice, st));
   double* out = (double*)(base + L.out);
-  HIP_TRY(launch_fill(out, p.out_elems, 0.0, st));
   const GridDev* grids = (const GridDev*)(base + L.grids);
   const double* lines = (const double*)(base + L.lines);
   const SegDev* segs = (const SegDev*)(base + L.segs);
@@ -268,22 +269,21 @@ int32_t enqueue_job(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L) {
   const RedDev* reds = (const RedDev*)(base + L.reds);
   const int32_t* items = (const int32_t*)(base + L.items);
   const bool mixed = p.precision == PS_PREC_MIXED;
-  size_t item_pos = 0;
-  s.n_contract = 0;
-  for (size_t pi = 0; pi < p.passes.size(); ++pi) {
-    const Pass& ps = p.passes[pi];
-    double* ws = (double*)(base + L.arrays + ps.ws_offset);
-    HIP_TRY(launch_eval(mixed, segs + ps.seg0, ps.seg1 - ps.seg0, ps.eval_blocks, grids, lines,
-                        (const ShellDev*)(base + L.shells), (const MEntry*)(base + L.ments),
-                        (const WColDev*)(base + L.wcols), st));
-    if ((int)s.ev_contract.size() < 2 * (int)(pi + 1)) {
-      hipEvent_t e0, e1;
-      HIP_TRY(hipEventCreate(&e0));
-      HIP_TRY(hipEventCreate(&e1));
-      s.ev_contract.push_back(e0);
-      s.ev_contract.push_back(e1);
-    }
-    HIP_TRY(hipEventRecord(s.ev_contract[2 * pi], st));
+  auto eval = [&](const Pass& ps) {
+    return launch_eval(mixed, segs + ps.seg0, ps.seg1 - ps.seg0, ps.eval_blocks, grids, lines,
+                       (const ShellDev*)(base + L.shells), (const MEntry*)(base + L.ments),
+                       (const WColDev*)(base + L.wcols), st);
+  };
+  if (k == 0) {
+    HIP_TRY(hipMemcpyAsync(base, s.pinned, L.meta_end, hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_fill(out, p.out_elems, 0.0, st));
+    if (!p.passes.empty()) HIP_TRY(eval(p.passes[0]));
+    return PS_OK;
+  }
+  const int pi = (k - 1) / 2;
+  const Pass& ps = p.passes[pi];
+  double* ws = (double*)(base + L.arrays + ps.ws_offset);
+  if (k % 2 == 1) {
     // one launch per tile shape: (ab|P) tiles, 64 x 64 tiles, narrow last-column tiles
     for (const auto& lc : ps.launches) {
       const int n = lc.tile1 - lc.tile0;
@@ -294,13 +294,16 @@ int32_t enqueue_job(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L) {
       else
         HIP_TRY(launch_contract_f64(sh.wm, sh.wn, sh.sc, tasks, tiles + lc.tile0, n, ws, st));
     }
-    HIP_TRY(hipEventRecord(s.ev_contract[2 * pi + 1], st));
-    s.n_contract++;
-    for (auto& ph : ps.red_by_phase) {
-      HIP_TRY(launch_reduce(tasks, reds, items + item_pos, (int)ph.size(), ws, st));
-      item_pos += ph.size();
-    }
+    return PS_OK;
   }
+  size_t item_pos = 0;
+  for (int q = 0; q < pi; ++q)
+    for (auto& ph : p.passes[q].red_by_phase) item_pos += ph.size();
+  for (auto& ph : ps.red_by_phase) {
+    HIP_TRY(launch_reduce(tasks, reds, items + item_pos, (int)ph.size(), ws, st));
+    item_pos += ph.size();
+  }
+  if (pi + 1 < (int)p.passes.size()) return eval(p.passes[pi + 1]) == hipSuccess ? PS_OK : PS_E_DEVICE;
   const int nb = p.n_bf, na = p.n_aux;
   HIP_TRY(launch_symmetrize(out + p.off_S, nb, st));
   HIP_TRY(launch_symmetrize(out + p.off_T, nb, st));
@@ -308,6 +311,36 @@ int32_t enqueue_job(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L) {
   HIP_TRY(launch_symmetrize(out + p.off_PQ, na, st));
   if (s.want_chol && na > 0)
     HIP_TRY(launch_cholesky(out + p.off_PQ, out + p.off_L, na, (int*)(base + L.status), st));
+  return PS_OK;
+}
+
+// Enqueue every step of a planned job on slot s (no synchronisation), each segment either launched
+// directly or, when `graphs` holds one executable per segment, as that segment's graph.  The events
+// that time the job and its contraction launches are recorded on the stream between segments (outside
+// any graph), so they are measured afresh on every run.
+int32_t enqueue_job(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, const std::vector<hipGraphExec_t>* graphs) {
+  hipStream_t st = s.stream;
+  while (s.ev_contract.size() < 2 * p.passes.size()) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    s.ev_contract.push_back(e);
+  }
+  HIP_TRY(hipEventRecord(s.ev_start, st));
+  s.n_contract = 0;
+  const int nseg = num_segments(p);
+  for (int k = 0; k < nseg; ++k) {
+    if (k % 2 == 1) HIP_TRY(hipEventRecord(s.ev_contract[k - 1], st));
+    if (graphs) {
+      HIP_TRY(hipGraphLaunch((*graphs)[k], st));
+    } else {
+      int32_t rc = enqueue_segment(ctx, s, p, L, k);
+      if (rc) return rc;
+    }
+    if (k % 2 == 1) {
+      HIP_TRY(hipEventRecord(s.ev_contract[k], st));
+      s.n_contract++;
+    }
+  }
   HIP_TRY(hipEventRecord(s.ev_kernels_done, st));
   return PS_OK;
 }
@@ -408,8 +441,8 @@ int32_t plan_job(ps_ctx* ctx, const ps_job* job, Plan& plan, Layout& L) {
 }
 
 void drop_graph(Slot& s) {
-  if (s.graph) (void)hipGraphExecDestroy(s.graph);
-  s.graph = nullptr;
+  for (auto g : s.graphs) (void)hipGraphExecDestroy(g);
+  s.graphs.clear();
 }
 
 int32_t prepare_slot(ps_ctx* ctx, Slot& s, const ps_job* job, Plan& plan, Layout& L) {
@@ -607,34 +640,39 @@ int32_t ps_compute(ps_ctx* ctx, const ps_job* job, ps_job_stats* st) {
   const Plan& plan = s.plan;
   const Layout& L = s.layout;
   int32_t rc = PS_OK;
-  if (repeat && !s.graph && !s.graph_failed) {
-    // second run of the same plan: capture its device work (kernels, the table copy, events; no
-    // memset nodes) into a graph, replayed from now on
-    if (hipStreamBeginCapture(s.stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
-      rc = enqueue_job(ctx, s, plan, L);
+  if (repeat && s.graphs.empty() && !s.graph_failed) {
+    // second run of the same plan: capture each segment of its device work (kernels, the table copy;
+    // no memset nodes) into a graph of its own, replayed from now on between the timing events
+    for (int k = 0; k < num_segments(plan) && !s.graph_failed; ++k) {
       hipGraph_t g = nullptr;
+      hipGraphExec_t x = nullptr;
+      if (hipStreamBeginCapture(s.stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        s.graph_failed = true;
+        break;
+      }
+      rc = enqueue_segment(ctx, s, plan, L, k);
       hipError_t e = hipStreamEndCapture(s.stream, &g);
-      if (rc == PS_OK && e == hipSuccess && g && hipGraphInstantiate(&s.graph, g, nullptr, nullptr, 0) != hipSuccess)
-        s.graph = nullptr;
+      if (rc == PS_OK && e == hipSuccess && g && hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess)
+        s.graphs.push_back(x);
+      else
+        s.graph_failed = true;
       if (g) (void)hipGraphDestroy(g);
       if (rc != PS_OK) {
+        drop_graph(s);
         s.plan_inputs.clear();
         return rc;
       }
     }
-    if (!s.graph) {
-      s.graph_failed = true;
+    if (s.graph_failed) {
+      drop_graph(s);
       (void)hipGetLastError();
     }
   }
-  if (repeat && s.graph) {
-    HIP_TRY(hipGraphLaunch(s.graph, s.stream));
-  } else {
-    rc = enqueue_job(ctx, s, plan, L);
-    if (rc) {
-      s.plan_inputs.clear();
-      return rc;
-    }
+  const bool replay = repeat && !s.graphs.empty();
+  rc = enqueue_job(ctx, s, plan, L, replay ? &s.graphs : nullptr);
+  if (rc) {
+    s.plan_inputs.clear();
+    return rc;
   }
   rc = enqueue_outputs(ctx, s, plan, L, *job);
   if (rc) {
@@ -644,7 +682,7 @@ int32_t ps_compute(ps_ctx* ctx, const ps_job* job, ps_job_stats* st) {
   HIP_TRY(hipStreamSynchronize(s.stream));
   double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   rc = finish_stats(ctx, s, plan, L, st, ms, 0.0);
-  if (st) st->graph_replay = (repeat && s.graph) ? 1 : 0;
+  if (st) st->graph_replay = replay ? 1 : 0;
   return rc;
 }
 

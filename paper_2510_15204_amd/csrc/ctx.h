@@ -43,8 +43,8 @@ struct Slot {
   std::vector<char> plan_inputs;  // serialised job inputs + tiling + budget; empty = no valid plan
   Plan plan;
   Layout layout;
-  // device work of that plan captured once it repeats, replayed as one graph launch
-  hipGraphExec_t graph = nullptr;
+  // device work of that plan captured once it repeats, replayed segment by segment as graph launches
+  std::vector<hipGraphExec_t> graphs;  // one per segment of the job's device work
   bool graph_failed = false;       // capture not possible on this stream: stay with stream launches
 };
 

@@ -16,8 +16,14 @@ int32_t plan_job(ps_ctx* ctx, const ps_job* job, Plan& plan, Layout& L);
 int32_t bind_slot(ps_ctx* ctx, Slot& s, const Plan& plan, const Layout& L, size_t extra_pinned, bool want_chol);
 // plan_job + bind_slot.
 int32_t prepare_slot(ps_ctx* ctx, Slot& s, const ps_job* job, Plan& plan, Layout& L);
-// Enqueue all device work of a prepared job on the slot's stream.
-int32_t enqueue_job(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L);
+// Segments of a job's device work: table copy + evaluation, then per pass its contraction launches
+// (odd segments) and its reductions + the next pass's evaluation or the final assembly (even).
+int num_segments(const Plan& p);
+int32_t enqueue_segment(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, int k);
+// Enqueue all device work of a prepared job on the slot's stream, with the timing events between the
+// segments; `graphs` (one executable per segment) replays captured segments instead of launching.
+int32_t enqueue_job(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L,
+                    const std::vector<hipGraphExec_t>* graphs = nullptr);
 // Enqueue the output copies (to the caller's buffers, or to `host_bounce` for host outputs when
 // non-null) and the end event.
 int32_t enqueue_outputs(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, const ps_job& job,
