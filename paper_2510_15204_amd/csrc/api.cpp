@@ -634,6 +634,7 @@ int32_t ps_compute(ps_ctx* ctx, const ps_job* job, ps_job_stats* st) {
   const bool repeat = !s.plan_inputs.empty() && s.plan_inputs == key;
   if (!repeat) {
     int32_t rc = prepare_slot(ctx, s, job, s.plan, s.layout);
+    ctx->sync_arena_bytes.store(s.arena_size);
     if (rc) return rc;
     s.plan_inputs = std::move(key);
   }

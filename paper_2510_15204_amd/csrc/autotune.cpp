@@ -22,6 +22,7 @@ int32_t time_candidate(ps_ctx* ctx, const ps_job* job, int reps, ps_tuning* out)
   Plan plan;
   Layout L;
   int32_t rc = prepare_slot(ctx, s, job, plan, L);
+  ctx->sync_arena_bytes.store(s.arena_size);
   if (rc) return rc;
   out->device_ms = DBL_MAX;
   out->contract_ms = DBL_MAX;

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <condition_variable>
 #include <cstdint>
 #include <deque>
@@ -79,6 +80,7 @@ struct ps_ctx {
   psint::Slot sync_slot;
   std::mutex sync_mu;  // held while ps_compute / ps_autotune use sync_slot; the serving dispatcher
                        // takes an idle sync_slot's arena back when a queued job needs the memory
+  std::atomic<size_t> sync_arena_bytes{0};  // sync_slot.arena_size as last published under sync_mu
   psint::ServeState* serve = nullptr;  // created by the first ps_submit, freed by ps_destroy
   void* ri_buf = nullptr;              // RI assembly scratch (grown on demand)
   size_t ri_buf_size = 0;

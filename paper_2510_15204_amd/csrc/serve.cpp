@@ -119,7 +119,7 @@ static void worker_loop(ps_ctx* ctx) {
     while (!S.queue.empty()) {
       auto t = S.queue.front();
       // the synchronous slot's arena (ps_compute on this context) shares the budget
-      size_t busy = ctx->sync_slot.arena_size;
+      size_t busy = ctx->sync_arena_bytes.load();
       int free_slot = -1;
       for (int si = 0; si < (int)S.slots.size(); ++si) {
         if (S.running[si]) busy += S.slots[si].arena_size;
@@ -138,14 +138,15 @@ static void worker_loop(ps_ctx* ctx) {
           ss.arena_size = 0;
           ss.plan_inputs.clear();
           drop_graph(ss);
+          ctx->sync_arena_bytes.store(0);
         }
         ctx->sync_mu.unlock();
         return true;
       };
       bool sync_busy = false;
-      if (busy + t->need_bytes > ctx->budget && ctx->sync_slot.arena) {
+      if (busy + t->need_bytes > ctx->budget && ctx->sync_arena_bytes.load() > 0) {
         sync_busy = !reclaim_sync();
-        busy = ctx->sync_slot.arena_size;
+        busy = ctx->sync_arena_bytes.load();
         for (int si = 0; si < (int)S.slots.size(); ++si)
           if (S.running[si]) busy += S.slots[si].arena_size;
       }
