@@ -67,15 +67,10 @@ void* pool_alloc(ps_ctx* ctx, size_t bytes, size_t* got) {
   DevicePool& P = ctx->pool;
   std::lock_guard<std::mutex> g(P.mu);
   auto take = [&](DevicePool::Chunk& c) -> void* {
-    for (auto it = c.free.begin(); it != c.free.end(); ++it) {
-      if (it->second < bytes) continue;
-      const size_t off = it->first, len = it->second;
-      c.free.erase(it);
-      if (len > bytes) c.free[off + bytes] = len - bytes;
-      *got = bytes;
-      return c.base + off;
-    }
-    return nullptr;
+    size_t off = 0;
+    if (!c.ranges.take(bytes, &off)) return nullptr;
+    *got = bytes;
+    return c.base + off;
   };
   for (auto& c : P.chunks)
     if (void* p = take(c)) return p;
@@ -87,8 +82,7 @@ void* pool_alloc(ps_ctx* ctx, size_t bytes, size_t* got) {
       (void)hipGetLastError();
       return nullptr;
     }
-    c.size = size;
-    c.free[0] = size;
+    c.ranges = RangeMap(size);
     P.total += size;
     P.chunks.push_back(c);
     return take(P.chunks.back());
@@ -105,9 +99,9 @@ void* pool_alloc(ps_ctx* ctx, size_t bytes, size_t* got) {
   // give back chunks without ranges in use (their memory is cleared by the driver before reuse)
   for (size_t i = 0; i < P.chunks.size();) {
     auto& c = P.chunks[i];
-    if (c.free.size() == 1 && c.free.begin()->first == 0 && c.free.begin()->second == c.size) {
+    if (c.ranges.unused()) {
       (void)hipFree(c.base);
-      P.total -= c.size;
+      P.total -= c.ranges.size();
       P.chunks.erase(P.chunks.begin() + i);
     } else {
       ++i;
@@ -122,22 +116,8 @@ void pool_release(ps_ctx* ctx, void* p, size_t bytes) {
   DevicePool& P = ctx->pool;
   std::lock_guard<std::mutex> g(P.mu);
   for (auto& c : P.chunks) {
-    if ((char*)p < c.base || (char*)p >= c.base + c.size) continue;
-    size_t off = (size_t)((char*)p - c.base), len = bytes;
-    auto next = c.free.lower_bound(off);
-    if (next != c.free.end() && next->first == off + len) {  // merge with the following range
-      len += next->second;
-      next = c.free.erase(next);
-    }
-    if (next != c.free.begin()) {  // merge with the preceding range
-      auto prev = std::prev(next);
-      if (prev->first + prev->second == off) {
-        off = prev->first;
-        len += prev->second;
-        c.free.erase(prev);
-      }
-    }
-    c.free[off] = len;
+    if ((char*)p < c.base || (char*)p >= c.base + c.ranges.size()) continue;
+    c.ranges.give((size_t)((char*)p - c.base), bytes);
     return;
   }
 }

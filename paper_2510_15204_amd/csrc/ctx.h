@@ -15,6 +15,7 @@
 
 #include "../../include/psint.h"
 #include "plan.h"
+#include "ranges.h"
 
 namespace psint {
 
@@ -59,8 +60,7 @@ struct ServeState;
 struct DevicePool {
   struct Chunk {
     char* base = nullptr;
-    size_t size = 0;
-    std::map<size_t, size_t> free;  // offset -> length of the free ranges, coalesced
+    RangeMap ranges;
   };
   std::mutex mu;
   std::vector<Chunk> chunks;
