@@ -338,7 +338,8 @@ def test_plan_reuse_for_repeated_jobs():
 
 
 def test_repeated_job_graph_replay_matches_eager():
-    """The second run of an unchanged job is captured into a HIP graph and later runs replay it: every
+    """The second run of an unchanged job is captured into HIP graphs (one per segment) and later runs
+    replay them: every
     replay, with other device work in between, equals the first (eager) run bit for bit, and the
     timing events inside the graph still report."""
     import torch
@@ -360,3 +361,31 @@ def test_repeated_job_graph_replay_matches_eager():
         assert np.array_equal(dev[k].cpu().numpy(), ref[k]), k
     c.close()
     other.close()
+
+
+def test_multi_pass_graph_replay_matches_eager_and_times_afresh():
+    """A job split into several memory passes is replayed as one captured graph per segment (the
+    evaluation, each pass's contraction, the reductions), with the timing events recorded between the
+    graphs: every replay equals the eager run bit for bit, and the contraction time is measured on
+    each replay rather than repeated from one run."""
+    xyz = np.array([[0.0, 0.0, 0.0], [1.9, 0.2, 0.0], [-0.4, 1.8, 0.3], [0.6, -0.5, 2.0]])
+    basis = [[a, 1, 0, 0, 1.2 + 0.3 * a] for a in range(4)] + [[a, 2, 1, 1, 1.0] for a in range(4)]
+    aux = [[a, 1, 0, 0, 2.5] for a in range(4)] + [[a, 2, 1, -1, 2.0] for a in range(4)]
+    job = MiniJob(xyz, [6, 1, 8, 1], basis, aux, Spec(10, 10, 8, 4, 3))
+    probe = psint.Context(0)
+    need = probe.plan_work(job)["device_bytes"]
+    probe.close()
+    c = psint.Context(0, budget_bytes=int(need * 0.3))
+    ref, st0, _ = c.compute(job)
+    assert st0["n_passes"] >= 2 and st0["graph_replay"] == 0
+    times = set()
+    for i in range(4):
+        out, st, _ = c.compute(job)
+        assert st["graph_replay"] == 1 and st["n_passes"] == st0["n_passes"]
+        for k in psint.OUTPUTS:
+            assert np.array_equal(out[k], ref[k]), (i, k)
+        assert 0 < st["contract_ms"] <= st["device_ms"]
+        times.add(round(st["contract_ms"], 6))
+    _say(f"{st0['n_passes']} passes, contraction ms over replays: {sorted(times)}")
+    assert len(times) > 1  # measured on every replay
+    c.close()
