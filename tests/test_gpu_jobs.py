@@ -339,9 +339,8 @@ def test_plan_reuse_for_repeated_jobs():
 
 def test_repeated_job_graph_replay_matches_eager():
     """The second run of an unchanged job is captured into HIP graphs (one per segment) and later runs
-    replay them: every
-    replay, with other device work in between, equals the first (eager) run bit for bit, and the
-    timing events inside the graph still report."""
+    replay them: every replay, with other device work in between, equals the first (eager) run bit
+    for bit, and the timing events between the graphs report."""
     import torch
     job = _tri_tz((8, 8, 6, 4, 3, 2.3, 0.25))
     c, other = psint.Context(0), psint.Context(0)
