@@ -858,14 +858,18 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
     return rows;
   };
   // Two-index tasks always take the second (64 x 64) shape.  An (ab|P) task takes it too when that
-  // issues less than 90% of the FLOPs of the main shape (narrow column ranges such as one third
-  // atom's auxiliary set); 64 x 64 tiles run about 10% slower per FLOP.
+  // issues less than 90% of the FLOPs of the main shape (short row ranges); 64 x 64 tiles run about
+  // 10% slower per FLOP.  Either shape's last column tile is narrowed to a multiple of 32 columns
+  // (below), so one third atom's auxiliary set (e.g. 165 = 128 + 37 columns) issues 192 columns
+  // in both and stays on the main shape.
   std::vector<char> small_task(p.tasks.size(), 1);
   for (size_t t = 0; t < p.tasks.size(); ++t) {
     const TaskHost& th = p.tasks[t];
     if (th.out_kind != 4) continue;
     auto issued = [&](const TileShape& sh) {
-      return (double)row_tiles(th, sh).size() * (double)((th.dev.ny + sh.bn() - 1) / sh.bn()) * sh.bm() * sh.bn();
+      const int full = th.dev.ny / sh.bn() * sh.bn();
+      const int cols = full + (th.dev.ny - full + 31) / 32 * 32;
+      return (double)row_tiles(th, sh).size() * sh.bm() * (double)cols;
     };
     small_task[t] = issued(shape2) < 0.9 * issued(shape) ? 1 : 0;
   }
