@@ -398,6 +398,8 @@ TileShape effective_shape(const ps_ctx* ctx, int32_t precision) {
     std::lock_guard<std::mutex> g(mu);
     t.slots = resident(t.wm, t.wn, t.sc);
     t.slots2 = resident(2, 2, t.sc);
+    for (int w = 1; w < t.wn && w <= 3; ++w) t.slots_n[w] = resident(t.wm, w, t.sc);
+    t.slots2n = resident(2, 1, t.sc);
   }
   return t;
 }

@@ -334,6 +334,11 @@ static void xcd_order(std::vector<TileDev>& tiles, int t0, int t1) {
       it->second.push_back(i);
     }
   }
+  // longest groups first (a group's tiles share one K range, so one length): each queue then runs
+  // its longest tiles first and the short ones fill the end of the launch
+  std::stable_sort(order_keys.begin(), order_keys.end(), [&](const auto& a, const auto& b) {
+    return tiles[groups[a][0]].nkc > tiles[groups[b][0]].nkc;
+  });
   std::vector<std::vector<int>> q(NX);
   std::vector<double> load(NX, 0.0);
   for (auto& key : order_keys) {
@@ -884,12 +889,12 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
     const size_t items = row_tiles(th, sh).size() * (size_t)((th.dev.ny + sh.bn() - 1) / sh.bn());
     grid_bytes[th.grid] += items * (size_t)sh.bm() * sh.bn() * 8;
   }
-  // reserve the K-split workspace (about 2048 extra partial tiles per launch), the output buffer and
+  // reserve the K-split workspace (up to 8192 extra partial tiles per launch), the output buffer and
   // the job's tables; the rest holds the arrays and per-item partial tiles of the pass's grids
   const size_t out_bytes = (size_t)p.out_elems * 8;
-  const size_t ws_cap1 = std::min<size_t>((size_t)4096 * shape.bm() * shape.bn() * 8, budget / 4);
-  const size_t ws_cap2 = std::min<size_t>((size_t)4096 * shape2.bm() * shape2.bn() * 8, budget / 16);
-  const size_t ws_cap3 = std::min<size_t>((size_t)4096 * shape.bm() * shape.bn() * 8, budget / 16);
+  const size_t ws_cap1 = std::min<size_t>((size_t)8192 * shape.bm() * shape.bn() * 8, budget / 8);
+  const size_t ws_cap2 = std::min<size_t>((size_t)8192 * shape2.bm() * shape2.bn() * 8, budget / 16);
+  const size_t ws_cap3 = std::min<size_t>((size_t)4 * 8192 * shape.bm() * shape.bn() * 8, budget / 16);
   const size_t ws_cap = ws_cap1 + ws_cap2 + ws_cap3;
   // tables (grids, shells, tasks, tiles, pair lists): the pair lists plus a small allowance
   const size_t tables = ((size_t)1 << 20) + budget / 256 + p.ints.size() * 4;
@@ -964,10 +969,10 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       TileShape gshape[NG] = {shape, shape2, shape, shape, shape, shape2};
       for (int w = 1; w <= 3; ++w) {
         gshape[1 + w].wn = w;
-        gshape[1 + w].slots = 0;
+        gshape[1 + w].slots = shape.slots_n[w];
       }
       gshape[5].wn = 1;
-      gshape[5].slots = 0;
+      gshape[5].slots = shape.slots2n;
       std::vector<Item> items[NG];
       double total_cost[NG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       for (int t = ps.task0; t < ps.task1; ++t) {
@@ -1020,15 +1025,39 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
         if (items[grp].empty()) continue;
         const TileShape& sh = gshape[grp];
         const int BM = sh.bm(), BN = sh.bn();
-        // K splits: aim for about 8 work-groups per CU over 256 CUs per launch, within the group's
-        // workspace reservation (one BM x BN FP64 partial tile per work-group)
+        // K splits: at least 2048 work-groups per launch (8 per CU over 256 CUs); launches of long tiles
+        // up to 6 per item while tiles keep 8192 chunks or more, so that the dispatch balances (a
+        // tile's fixed cost, its first stage and its partial-tile write, stays small against its
+        // length); all within the group's workspace reservation (one BM x BN FP64 partial tile per
+        // work-group)
         const size_t cap = grp == 0 ? ws_cap1 : (grp == 1 ? ws_cap2 : ws_cap3 / std::max(1, n_narrow));
         const double ws_tiles = (double)cap / ((double)BM * BN * 8);
-        const double target = std::max((double)items[grp].size(), std::min(2048.0, ws_tiles));
+        const double want_tiles =
+            std::max(2048.0, std::min(6.0 * (double)items[grp].size(), total_cost[grp] / 8192.0));
+        const double target = std::max((double)items[grp].size(), std::min(want_tiles, ws_tiles));
         const int tg0 = (int)p.tiles.size();
         const size_t nit = items[grp].size();
         std::vector<int64_t> nsv(nit), nstv(nit);
         const bool fill_ws = (double)nit >= ws_tiles;
+        // tile length bound: the smallest L for which ceil(cost / L) splits per item total at most the
+        // target, so that no tile of the launch is longer than L (splitting each item in proportion
+        // to its cost and rounding left one launch's tiles up to twice as long as others)
+        double len_bound = 1.0;
+        if (p.ksplit_override <= 0 && !fill_ws && nit > 0) {
+          double hi = 0.0;
+          for (const Item& it : items[grp]) hi = std::max(hi, it.cost);
+          double lo = std::min(hi, total_cost[grp] / target);
+          auto splits = [&](double L) {
+            double n = 0.0;
+            for (const Item& it : items[grp]) n += std::ceil(it.cost / L - 1e-9);
+            return n;
+          };
+          for (int k = 0; k < 60; ++k) {
+            const double mid = 0.5 * (lo + hi);
+            if (splits(mid) <= target) hi = mid; else lo = mid;
+          }
+          len_bound = hi;
+        }
         int64_t total_ns = 0;
         for (size_t ii = 0; ii < nit; ++ii) {
           const Item& it = items[grp][ii];
@@ -1039,7 +1068,7 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
           else if (fill_ws)
             ns = 1;  // the items alone fill the K-split allowance: one partial tile each
           else
-            ns = (int64_t)std::llround(target * it.cost / std::max(total_cost[grp], 1.0));
+            ns = (int64_t)std::ceil(it.cost / len_bound - 1e-9);
           const int64_t nst = nch / TileShape::SC_MAX;  // whole stages (nch is a multiple of 16)
           ns = std::max<int64_t>(1, std::min<int64_t>(ns, std::max<int64_t>(1, nst / 8)));
           nsv[ii] = ns;
@@ -1050,7 +1079,8 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
         // longest tiles once more until the last wave is full (its tiles would otherwise leave CUs
         // idle while the launch drains)
         if (sh.slots > 0 && p.ksplit_override <= 0 && !fill_ws && total_ns > 0) {
-          const int64_t want = (total_ns + sh.slots - 1) / sh.slots * sh.slots;
+          int64_t want = (total_ns + sh.slots - 1) / sh.slots * sh.slots;
+          if ((double)want > ws_tiles) want = total_ns;  // beyond the workspace reservation: no rounding
           while (total_ns < want) {
             int64_t best = -1;
             double best_len = 0.0;

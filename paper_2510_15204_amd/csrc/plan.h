@@ -19,6 +19,8 @@ struct TileShape {
   int slots = 0;                          // work-groups of this shape resident on the device at once
                                           // (0 = unknown: no rounding of the K splits)
   int slots2 = 0;                         // the same for the 64 x 64 two-index shape
+  int slots_n[4] = {0, 0, 0, 0};          // the same for this shape narrowed to wn = 1..3 (index wn)
+  int slots2n = 0;                        // the same for the 64 x 32 shape
   int bm() const { return 32 * wm; }
   int bn() const { return 32 * wn; }
   int maxuv() const { return bm() + 4; }  // staged U + V columns per tile
