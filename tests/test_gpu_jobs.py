@@ -79,6 +79,37 @@ def test_benchmark_workload_sampled_parity(ctx):
         assert np.max(np.abs(L @ L.T - PQ)) < 1e-11 * np.max(np.abs(PQ))
 
 
+@pytest.mark.parametrize("name,prec", [("triatomic_5z", "mixed"), ("hydrocarbon9", "mixed"),
+                                       ("hydrocarbon9", "fp64")])
+def test_larger_workloads_sampled_parity(name, prec):
+    """The triatomic 5Z job (three refined 128x128x64-point grids, auxiliaries up to l = 6) and the
+    hydrocarbon job (252 grids of 64-128 points per axis, several memory passes, contraction launches
+    balanced over uneven grids) at full size with the default tiling, as the benchmark runs them,
+    device outputs: sampled elements of every kind against the oracle, within 1e-10 in FP64 and
+    within MIXED_REL_TOL of each type's largest element in mixed precision.  A context of its own,
+    released at the end: the hydrocarbon job reserves most of the device memory."""
+    job = getattr(W, name)()
+    _say(f"{job.name} {prec}: n_bf={job.n_bf} n_aux={job.n_aux}")
+    c = psint.Context(0)
+    try:
+        got, st, rc = c.compute(job, device=True, precision=prec)
+        _say(f"passes={st['n_passes']} device_ms={st['device_ms']:.1f} rc={rc}")
+        host = {k: v.cpu().numpy() for k, v in got.items()}
+        del got
+    finally:
+        c.close()
+    kinds, I, J, K = sample(job, 60, 11)
+    ref, _ = O.compute_elements(job, kinds, I, J, K)
+    err = np.abs(pick(host, kinds, I, J, K) - ref)
+    for k in range(5):
+        scale = np.max(np.abs(host[KINDS[k]]))
+        e = err[kinds == k].max()
+        _say(f"{KINDS[k]}: max abs err {e:.2e} (largest element {scale:.2e})")
+        assert e < (1e-10 if prec == "fp64" else MIXED_REL_TOL * scale), (KINDS[k], e, scale)
+    for k in ("S", "T", "V", "PQ"):
+        assert np.array_equal(host[k], host[k].T)
+
+
 def _pd_metric_job():
     """Three atoms, 75 auxiliary functions with well-separated exponents up to l = 3: (P|Q) has
     condition number about 2e4 on a 10x10x8-cell grid, and 75 = two full 32-column panels plus a
