@@ -196,8 +196,10 @@ int32_t ps_autotune(ps_ctx* ctx, const ps_job* job, int32_t reps, ps_tuning* bes
  * Inputs as ps_compute writes them: abP [P][a][b] (n_aux x n_bf x n_bf), L n_aux x n_aux lower
  * (the upper triangle is not read).  Outputs (NULL = not wanted): B n_aux x n_pair and eri
  * n_pair x n_pair, row-major FP64.  All four arrays live on the host (location PS_OUT_HOST) or on
- * the context's device (PS_OUT_DEVICE); device scratch (grown on demand, freed by ps_destroy) must
- * fit the context's budget, else PS_E_NOMEM.  *device_ms (may be NULL) receives the kernels' time. */
+ * the context's device (PS_OUT_DEVICE).  Device scratch comes from the context's device memory
+ * (the budget jobs use; returned to it when the call ends); PS_E_NOMEM if it does not fit.  Runs on
+ * the context's synchronous stream, one call at a time with ps_compute and ps_autotune.  *device_ms
+ * (may be NULL) receives the kernels' time. */
 int32_t ps_ri_assemble(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, int32_t location, const double* abP,
                        const double* L, double* B, double* eri, double* device_ms);
 

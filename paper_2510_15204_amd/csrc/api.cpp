@@ -427,6 +427,18 @@ void drop_graph(Slot& s) {
   s.graphs.clear();
 }
 
+void release_sync_arena(ps_ctx* ctx) {
+  Slot& s = ctx->sync_slot;
+  if (!s.arena) return;
+  (void)hipStreamSynchronize(s.stream);
+  pool_release(ctx, s.arena, s.arena_size);
+  s.arena = nullptr;
+  s.arena_size = 0;
+  s.plan_inputs.clear();
+  drop_graph(s);
+  ctx->sync_arena_bytes.store(0);
+}
+
 int32_t prepare_slot(ps_ctx* ctx, Slot& s, const ps_job* job, Plan& plan, Layout& L) {
   s.plan_inputs.clear();  // the slot's staged tables change
   drop_graph(s);
@@ -546,7 +558,6 @@ int32_t ps_destroy(ps_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   slot_free(ctx, ctx->sync_slot);
   pool_destroy(ctx);
-  if (ctx->ri_buf) (void)hipFree(ctx->ri_buf);
   delete ctx;
   return PS_OK;
 }

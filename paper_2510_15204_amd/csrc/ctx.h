@@ -82,8 +82,6 @@ struct ps_ctx {
                        // takes an idle sync_slot's arena back when a queued job needs the memory
   std::atomic<size_t> sync_arena_bytes{0};  // sync_slot.arena_size as last published under sync_mu
   psint::ServeState* serve = nullptr;  // created by the first ps_submit, freed by ps_destroy
-  void* ri_buf = nullptr;              // RI assembly scratch (grown on demand)
-  size_t ri_buf_size = 0;
   psint::DevicePool pool;              // slot arenas
 };
 

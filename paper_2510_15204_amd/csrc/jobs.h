@@ -35,6 +35,9 @@ int32_t ensure_pinned(ps_ctx* ctx, Slot& s, size_t bytes);
 int32_t ensure_arena(ps_ctx* ctx, Slot& s, size_t bytes);
 // Destroy the slot's captured graph (its kernels refer to the slot's current arena and tables).
 void drop_graph(Slot& s);
+// Give the arena ps_compute keeps for a repeat of its last job back to the device pool, with the
+// plan and graphs that refer to it.  The caller holds ctx->sync_mu.
+void release_sync_arena(ps_ctx* ctx);
 size_t output_bytes(const Plan& p, const ps_job& job);
 
 }  // namespace psint

@@ -13,9 +13,11 @@
 #include <chrono>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "ctx.h"
+#include "jobs.h"
 
 namespace psint {
 
@@ -219,20 +221,21 @@ using namespace psint;
 
 namespace {
 
-int32_t ensure_ri_buffer(ps_ctx* ctx, size_t bytes) {
-  if (ctx->ri_buf_size >= bytes) return PS_OK;
-  if (ctx->ri_buf) (void)hipFree(ctx->ri_buf);
-  ctx->ri_buf = nullptr;
-  ctx->ri_buf_size = 0;
-  hipError_t e = hipMalloc(&ctx->ri_buf, bytes);
-  if (e != hipSuccess) {
-    ctx->ri_buf = nullptr;
-    ctx->err = std::string("ri: hipMalloc: ") + hipGetErrorString(e);
-    return PS_E_NOMEM;
+// The call's device scratch, taken from the context's device pool (the same budget and memory as
+// job arenas) and given back when the call returns; the stream is drained first, so no kernel of
+// the call still uses it, also after an error.
+struct RiScratch {
+  ps_ctx* ctx;
+  hipStream_t st;
+  void* p = nullptr;
+  size_t size = 0;
+  RiScratch(ps_ctx* c, hipStream_t s) : ctx(c), st(s) {}
+  ~RiScratch() {
+    if (!p) return;
+    (void)hipStreamSynchronize(st);
+    pool_release(ctx, p, size);
   }
-  ctx->ri_buf_size = bytes;
-  return PS_OK;
-}
+};
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -255,6 +258,8 @@ extern "C" int32_t ps_ri_assemble(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, int3
     return PS_E_INVALID;
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
+  // the synchronous stream is shared with ps_compute and ps_autotune: one of them at a time
+  std::lock_guard<std::mutex> sync_guard(ctx->sync_mu);
   const bool dev = location == PS_OUT_DEVICE;
   const int64_t nb = n_bf, na = n_aux, npair = nb * (nb + 1) / 2;
   const size_t abp_b = (size_t)na * nb * nb * 8, l_b = (size_t)na * na * 8, x_b = (size_t)na * npair * 8,
@@ -286,10 +291,23 @@ extern "C" int32_t ps_ri_assemble(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, int3
     ctx->err = buf;
     return PS_E_NOMEM;
   }
-  int32_t rc = ensure_ri_buffer(ctx, total);
-  if (rc) return rc;
-  char* base = (char*)ctx->ri_buf;
   hipStream_t st = ctx->sync_slot.stream;
+  RiScratch scratch(ctx, st);
+  scratch.p = pool_alloc(ctx, total, &scratch.size);
+  if (!scratch.p) {
+    // the arena kept for a repeat of the last ps_compute job is the one other user of the budget
+    // that is idle now (this call holds sync_mu)
+    release_sync_arena(ctx);
+    scratch.p = pool_alloc(ctx, total, &scratch.size);
+  }
+  if (!scratch.p) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "ri: no device memory for %.2f GB of scratch within the %.2f GB budget", total / 1e9,
+             ctx->budget / 1e9);
+    ctx->err = buf;
+    return PS_E_NOMEM;
+  }
+  char* base = (char*)scratch.p;
   const double* d_abp = dev ? abP : (const double*)(base + off_abp);
   const double* d_l = dev ? L : (const double*)(base + off_l);
   double* d_x = (double*)(base + off_x);

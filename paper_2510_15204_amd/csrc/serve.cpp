@@ -130,16 +130,7 @@ static void worker_loop(ps_ctx* ctx) {
       // the pool, with the plan and graph that refer to it; false if a ps_compute holds the slot
       auto reclaim_sync = [&]() {
         if (!ctx->sync_mu.try_lock()) return false;
-        Slot& ss = ctx->sync_slot;
-        if (ss.arena) {
-          (void)hipStreamSynchronize(ss.stream);
-          pool_release(ctx, ss.arena, ss.arena_size);
-          ss.arena = nullptr;
-          ss.arena_size = 0;
-          ss.plan_inputs.clear();
-          drop_graph(ss);
-          ctx->sync_arena_bytes.store(0);
-        }
+        release_sync_arena(ctx);
         ctx->sync_mu.unlock();
         return true;
       };

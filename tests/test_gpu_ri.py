@@ -79,6 +79,50 @@ def test_ri_device_path_equals_host_path(ctx, oracle_inputs):
     assert e3 is None and np.array_equal(B3, Bh)
 
 
+def test_ri_scratch_shares_the_context_budget(ctx, oracle_inputs):
+    """RI scratch comes from the context's device memory.  With a budget that holds the job's arena
+    or the scratch of an RI call but not both, the RI call takes back the arena ps_compute keeps for a
+    repeat of its last job (so the repeat is planned again rather than replayed); the job's results
+    match the oracle, and RI equals RI on a context without the limit."""
+    job, ref, _, _ = oracle_inputs
+    gran = 2 << 20  # the device pool's allocation granularity
+    up = lambda b: (b + gran - 1) // gran * gran  # noqa: E731
+    # RI inputs of their own size (88 basis functions, 3916 pairs, 75 auxiliaries): scratch ~130 MB
+    rng = np.random.default_rng(5)
+    nb, na = 88, len(job.aux)
+    abP = rng.standard_normal((na, nb, nb))
+    L = np.tril(rng.uniform(0.1, 0.2, (na, na)), -1) + np.diag(rng.uniform(1.0, 2.0, na))
+    npair = nb * (nb + 1) // 2
+    ntile = (npair + 63) // 64
+    ri_bytes = 0
+    for b in (na * nb * nb * 8, na * na * 8, na * npair * 8, na * npair * 8, na * na * 8,
+              ntile * (ntile + 1) // 2 * 8, npair * npair * 8):  # host staging, X, B, G, tiles, eri
+        ri_bytes += (b + 255) // 256 * 256
+    ri_bytes = up(ri_bytes)
+    arena = up(ctx.plan_work(job)["device_bytes"])
+    budget = up(ri_bytes + arena // 2)
+    c = psint.Context(0, budget_bytes=budget)
+    try:
+        a2 = up(c.plan_work(job)["device_bytes"])
+        _say(f"arena {a2 / 1e6:.1f} MB, RI scratch {ri_bytes / 1e6:.1f} MB, budget {budget / 1e6:.1f} MB")
+        assert a2 + ri_bytes > budget >= max(a2, ri_bytes)
+        out, _, rc = c.compute(job)
+        assert rc == psint.PS_OK
+        B1, e1, _ = c.ri_assemble(abP, L)
+        out2, st2, _ = c.compute(job)
+        B2, e2, _ = c.ri_assemble(abP, L)
+    finally:
+        c.close()
+    assert st2["graph_replay"] == 0
+    for k in ("S", "T", "V", "PQ", "abP"):
+        assert np.max(np.abs(out[k] - ref[k])) < 1e-10
+    for k in ("S", "T", "V", "PQ", "PQ_chol", "abP"):
+        assert np.array_equal(out2[k], out[k])
+    B0, e0, _ = ctx.ri_assemble(abP, L)
+    for x, y in ((B1, B0), (e1, e0), (B2, B0), (e2, e0)):
+        assert np.array_equal(x, y)
+
+
 def test_ri_end_to_end_closed_forms(ctx):
     """GPU quadrature + GPU Cholesky + GPU RI on 1s(zeta = 1) atoms with 1s(2) auxiliaries: the
     densities lie in the auxiliary span, so (aa|aa) = 5/8 and (aa|bb) = J(R) exactly (up to the grid)."""
