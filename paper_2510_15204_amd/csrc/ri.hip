@@ -1,11 +1,12 @@
 // RI assembly (eq. 14): B = L^-1 A with A[P][ab] = (ab|P) over canonical pairs a >= b, then the
-// electron-repulsion matrix eri[ab][cd] = sum_R B[R][ab] B[R][cd].  Three kernels, all FP64:
+// electron-repulsion matrix eri[ab][cd] = sum_R B[R][ab] B[R][cd].  Kernels, all FP64:
 //   ri_gather_kernel  (ab|P) [P][a][b] -> A [P][ab]                 (HBM-bound copy)
 //   ri_inv_kernel     inverses of the 32 x 32 diagonal blocks of L (substitution, one per work-group)
 //   ri_offdiag_kernel L times those inverses below the diagonal blocks
-//   ri_solve_kernel   one block step of the forward substitution as a product on FP64 MFMA
-//   ri_syrk_kernel    64 x 64 output tiles on or above the diagonal, v_mfma_f64_16x16x4f64 with the
-//                     16-row slices of B staged in LDS; the mirror tile is written through an LDS
+//   ri_subst_kernel   the whole forward substitution on LDS strips of X (n_aux <= 1024)
+//   ri_solve_kernel   otherwise one block step of it per launch, as a product on FP64 MFMA
+//   ri_syrk_kernel    128 x 128 output tiles on or above the diagonal, v_mfma_f64_16x16x4f64 with
+//                     the 16-row slices of B staged in LDS; the mirror tile is written through an LDS
 //                     transpose so both halves are stored with coalesced rows
 #include <hip/hip_runtime.h>
 
@@ -139,80 +140,181 @@ __global__ __launch_bounds__(256) void ri_solve_kernel(const double* __restrict_
       }
 }
 
-constexpr int SY_T = 64;   // output tile
-constexpr int SY_K = 16;   // rows of B per stage
+// The whole forward substitution in one launch while a strip of X fits in LDS: the columns of X
+// (pairs ab) are independent, so a work-group takes SB_W of them over all n_aux rows and runs every
+// block step on its LDS copy, B_k = G_kk X_k and X_i -= G_ik X_k for the 16-row blocks below, with
+// G (L2-resident) as the MFMA A operand.  Larger n_aux: one launch per block step
+// (ri_solve_kernel).
+constexpr int SB_W = 16;                   // columns of X per work-group
+constexpr int SB_LD = SB_W + 2;            // padded LDS row, doubles
+constexpr int SB_MAX_NA = 1024;            // 1024 x 18 doubles = 144 KB of LDS
+constexpr int SB_MAX_LDS = SB_MAX_NA * SB_LD * 8;
 
-// C = X^T X for X (nk x n, row-major); tile list holds (ti, tj) with ti <= tj.
-__global__ __launch_bounds__(256) void ri_syrk_kernel(const double* __restrict__ X, int nk, int64_t n,
-                                                     const int2* __restrict__ tiles, double* __restrict__ C) {
-  __shared__ double As[SY_K][SY_T], Bs[SY_K][SY_T];
-  __shared__ double Ct[SY_T][SY_T + 1];
+__global__ __launch_bounds__(256) void ri_subst_kernel(const double* __restrict__ G, int na, int64_t n,
+                                                      const double* __restrict__ X, double* __restrict__ Bo) {
+  extern __shared__ __attribute__((aligned(16))) double Xs[];  // na_pad rows x SB_LD
+  const int na_pad = (na + TR_ROWS - 1) / TR_ROWS * TR_ROWS;
+  const int64_t c0 = (int64_t)blockIdx.x * SB_W;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int kl = lane >> 4, lc = lane & 15;
+  for (int e = tid; e < na_pad * SB_W; e += 256) {
+    const int r = e / SB_W, c = e - r * SB_W;
+    Xs[r * SB_LD + c] = (r < na && c0 + c < n) ? X[(int64_t)r * n + c0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < na_pad; k0 += TR_ROWS) {
+    // The 16-row blocks j of rows k0 + 16 j: j = 0, 1 form B_k = G_kk X_k (held in registers), the
+    // others X_i -= G_ik X_k (G_ik = L_ik D_k already holds the diagonal block's inverse); all read
+    // X_k as it stands, and B_k replaces it once every read is done.  Wave w takes j = w, w + 4, ...,
+    // four blocks at a time: their G operands are loaded together and their MFMA chains interleave.
+    const int nrb = (na_pad - k0) / 16;
+    d4_t bk = (d4_t){0.0, 0.0, 0.0, 0.0};
+    for (int j0 = wave; j0 < nrb; j0 += 16) {
+      double a[4][TR_ROWS / 4];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int gr = k0 + 16 * (j0 + 4 * jj) + lc;
+#pragma unroll
+        for (int st = 0; st < TR_ROWS / 4; ++st) {
+          const int q = k0 + 4 * st + kl;
+          a[jj][st] = (gr < na && q < na) ? G[(int64_t)gr * na + q] : 0.0;
+        }
+      }
+      d4_t u[4];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) u[jj] = (d4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < TR_ROWS / 4; ++st) {
+        const double xv = Xs[(k0 + 4 * st + kl) * SB_LD + lc];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) u[jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[jj][st], xv, u[jj], 0, 0, 0);
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int j = j0 + 4 * jj;
+        if (j < 2) {
+          bk = u[jj];
+        } else if (j < nrb) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Xs[(k0 + 16 * j + 4 * r + kl) * SB_LD + lc] -= u[jj][r];
+        }
+      }
+    }
+    __syncthreads();
+    if (wave < 2) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Xs[(k0 + 16 * wave + 4 * r + kl) * SB_LD + lc] = bk[r];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < na * SB_W; e += 256) {
+    const int r = e / SB_W, c = e - r * SB_W;
+    if (c0 + c < n) Bo[(int64_t)r * n + c0 + c] = Xs[r * SB_LD + c];
+  }
+}
+
+constexpr int SY_T = 128;  // output tile (4 waves in 2 x 2, 64 x 64 each: 4 x 4 MFMA blocks)
+constexpr int SY_K = 16;   // rows of B per stage
+constexpr int SY_LD = SY_T + 16;  // padded LDS row, doubles: rows k and k + 1 fall in opposite bank halves
+
+// C = X^T X for X (nk x n, row-major); tile list holds (ti, tj) with ti <= tj.  Each stage's 16 rows
+// of the tile's two column ranges are loaded into registers while the MFMAs of the previous stage
+// run and then stored into the other of two LDS buffers, so one barrier per stage suffices.  The
+// tile is stored from the accumulators with 16 consecutive columns per row; off the diagonal its
+// transpose goes through a 16 x 16 LDS block per wave, so that it is stored with coalesced rows too.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void ri_syrk_kernel(
+    const double* __restrict__ X, int nk, int64_t n, const int2* __restrict__ tiles, double* __restrict__ C) {
+  constexpr int BUF = SY_K * SY_LD;
+  __shared__ __attribute__((aligned(16))) double As[2 * BUF];
+  __shared__ __attribute__((aligned(16))) double Bs[2 * BUF];
   const int2 tl = tiles[blockIdx.x];
   const int64_t i0 = (int64_t)tl.x * SY_T, j0 = (int64_t)tl.y * SY_T;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wi = wave >> 1, wj = wave & 1, kl = lane >> 4, lc = lane & 15;
-  d4_t acc[2][2];
+  const int wm = wave >> 1, wn = wave & 1, kl = lane >> 4, lc = lane & 15;
+  d4_t acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = (d4_t){0.0, 0.0, 0.0, 0.0};
-  // each thread stages 4 + 4 values of a 16-row slice; the next slice is loaded into registers
-  // while the current one feeds the MFMAs
-  constexpr int PER = SY_K * SY_T / 256;
+    for (int b = 0; b < 4; ++b) acc[a][b] = (d4_t){0.0, 0.0, 0.0, 0.0};
+  constexpr int PER = SY_K * SY_T / 256;  // values per thread and operand per stage
   double ra[PER], rb[PER];
+  const int lcol = tid & (SY_T - 1), lrow = tid / SY_T;  // thread's column, first row (rows step by 2)
+  // loads without branches: out-of-range rows and columns read a clamped (valid) address, and are
+  // replaced by zero only when stored to LDS, after the MFMAs that hide the loads' latency
+  const bool ain = i0 + lcol < n, bin = j0 + lcol < n;
+  const double* xa = X + (ain ? i0 + lcol : n - 1);
+  const double* xb = X + (bin ? j0 + lcol : n - 1);
   auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = tid + 256 * q, kk = e / SY_T, c = e - kk * SY_T;
-      const bool kin = k0 + kk < nk;
-      ra[q] = (kin && i0 + c < n) ? X[(int64_t)(k0 + kk) * n + i0 + c] : 0.0;
-      rb[q] = (kin && j0 + c < n) ? X[(int64_t)(k0 + kk) * n + j0 + c] : 0.0;
+      const int64_t off = (int64_t)min(k0 + lrow + 2 * q, nk - 1) * n;
+      ra[q] = xa[off];
+      rb[q] = xb[off];
+    }
+  };
+  auto store = [&](int buf, int k0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const bool kin = k0 + lrow + 2 * q < nk;
+      As[buf * BUF + (lrow + 2 * q) * SY_LD + lcol] = (kin && ain) ? ra[q] : 0.0;
+      Bs[buf * BUF + (lrow + 2 * q) * SY_LD + lcol] = (kin && bin) ? rb[q] : 0.0;
     }
   };
   load(0);
-  for (int k0 = 0; k0 < nk; k0 += SY_K) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + 256 * q, kk = e / SY_T, c = e - kk * SY_T;
-      As[kk][c] = ra[q];
-      Bs[kk][c] = rb[q];
-    }
-    __syncthreads();
-    if (k0 + SY_K < nk) load(k0 + SY_K);
+  store(0, 0);
+  __syncthreads();
+  const int nst = (nk + SY_K - 1) / SY_K;
+  for (int st = 0; st < nst; ++st) {
+    const bool more = st + 1 < nst;
+    if (more) load((st + 1) * SY_K);
+    const double* Ac = As + (st & 1) * BUF;
+    const double* Bc = Bs + (st & 1) * BUF;
 #pragma unroll
     for (int s = 0; s < SY_K / 4; ++s) {
-      double av[2], bv[2];
+      double av[4], bv[4];
 #pragma unroll
-      for (int m = 0; m < 2; ++m) av[m] = As[4 * s + kl][wi * 32 + m * 16 + lc];
+      for (int m = 0; m < 4; ++m) av[m] = Ac[(4 * s + kl) * SY_LD + wm * 64 + m * 16 + lc];
 #pragma unroll
-      for (int m = 0; m < 2; ++m) bv[m] = Bs[4 * s + kl][wj * 32 + m * 16 + lc];
+      for (int m = 0; m < 4; ++m) bv[m] = Bc[(4 * s + kl) * SY_LD + wn * 64 + m * 16 + lc];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
+    if (more) store((st + 1) & 1, (st + 1) * SY_K);
+    __syncthreads();
   }
-  // tile -> LDS, then row-major stores of the tile and (off the diagonal) of its transpose
-  __syncthreads();
+  // the tile: accumulator register r of lane (kl, lc) is row 4 r + kl, column lc of its 16 x 16 block
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Ct[wi * 32 + a * 16 + 4 * r + kl][wj * 32 + b * 16 + lc] = acc[a][b][r];
-  __syncthreads();
-  for (int e = tid; e < SY_T * SY_T; e += 256) {
-    const int r = e / SY_T, c = e - r * SY_T;
-    if (i0 + r < n && j0 + c < n) C[(i0 + r) * n + j0 + c] = Ct[r][c];
-  }
-  if (tl.x != tl.y) {
-    for (int e = tid; e < SY_T * SY_T; e += 256) {
-      const int c = e / SY_T, r = e - c * SY_T;
-      if (i0 + r < n && j0 + c < n) C[(j0 + c) * n + i0 + r] = Ct[r][c];
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = i0 + wm * 64 + a * 16 + 4 * r + kl, col = j0 + wn * 64 + b * 16 + lc;
+        if (row < n && col < n) C[row * n + col] = acc[a][b][r];
+      }
+  if (tl.x == tl.y) return;  // (uniform) a diagonal tile holds both halves already
+  // the transpose, block by block through this wave's 16 x 17 LDS patch
+  double* Tw = As + wave * 16 * 17;
+  __syncthreads();  // every wave is done with As
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Tw[(4 * r + kl) * 17 + lc] = acc[a][b][r];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x = 4 * r + kl;  // column of the block = row of the transpose
+        const int64_t row = j0 + wn * 64 + b * 16 + x, col = i0 + wm * 64 + a * 16 + lc;
+        if (row < n && col < n) C[row * n + col] = Tw[lc * 17 + x];
+      }
+      __syncthreads();
     }
-  }
 }
 
 }  // namespace psint
@@ -321,10 +423,21 @@ extern "C" int32_t ps_ri_assemble(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, int3
   }
   std::vector<int2> tl;
   if (eri) {
+    // upper-triangle tiles row by row, cut into 8 contiguous runs, one per XCD (work-groups go to
+    // XCD blockIdx mod 8): the tiles of one run share their row block X[:, i0 .. i0 + 127] in that
+    // XCD's L2
     const int nt = (int)((npair + SY_T - 1) / SY_T);
-    tl.reserve(ntiles);
+    std::vector<int2> rows;
+    rows.reserve(ntiles);
     for (int i = 0; i < nt; ++i)
-      for (int j = i; j < nt; ++j) tl.push_back(make_int2(i, j));
+      for (int j = i; j < nt; ++j) rows.push_back(make_int2(i, j));
+    constexpr size_t NX = 8;
+    size_t beg[NX + 1];
+    for (size_t x = 0; x <= NX; ++x) beg[x] = rows.size() * x / NX;
+    tl.reserve(rows.size());
+    for (size_t r = 0; tl.size() < rows.size(); ++r)
+      for (size_t x = 0; x < NX; ++x)
+        if (beg[x] + r < beg[x + 1]) tl.push_back(rows[beg[x] + r]);
     RI_TRY(hipMemcpyAsync(d_tiles, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, st));
   }
   hipEvent_t e0, e1;
@@ -346,12 +459,22 @@ extern "C" int32_t ps_ri_assemble(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, int3
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(ri_offdiag_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d_l, n_aux, d_g);
     RI_TRY(hipGetLastError());
-    for (int r0 = 0; r0 < n_aux; r0 += TR_ROWS) {
-      const int below = n_aux - std::min(n_aux, r0 + TR_ROWS);
-      hipLaunchKernelGGL(ri_solve_kernel,
-                         dim3((unsigned)((npair + UP_T - 1) / UP_T), (unsigned)(1 + (below + UP_T - 1) / UP_T)),
-                         dim3(256), 0, st, (const double*)d_g, n_aux, npair, d_x, d_b, r0);
+    if (n_aux <= SB_MAX_NA) {
+      static const hipError_t attr =
+          hipFuncSetAttribute((const void*)ri_subst_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, SB_MAX_LDS);
+      RI_TRY(attr);
+      const size_t lds = (size_t)((n_aux + TR_ROWS - 1) / TR_ROWS * TR_ROWS) * SB_LD * sizeof(double);
+      hipLaunchKernelGGL(ri_subst_kernel, dim3((unsigned)((npair + SB_W - 1) / SB_W)), dim3(256), lds, st,
+                         (const double*)d_g, n_aux, npair, (const double*)d_x, d_b);
       RI_TRY(hipGetLastError());
+    } else {
+      for (int r0 = 0; r0 < n_aux; r0 += TR_ROWS) {
+        const int below = n_aux - std::min(n_aux, r0 + TR_ROWS);
+        hipLaunchKernelGGL(ri_solve_kernel,
+                           dim3((unsigned)((npair + UP_T - 1) / UP_T), (unsigned)(1 + (below + UP_T - 1) / UP_T)),
+                           dim3(256), 0, st, (const double*)d_g, n_aux, npair, d_x, d_b, r0);
+        RI_TRY(hipGetLastError());
+      }
     }
   }
   if (eri) {

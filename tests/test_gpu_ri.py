@@ -93,7 +93,7 @@ def test_ri_scratch_shares_the_context_budget(ctx, oracle_inputs):
     abP = rng.standard_normal((na, nb, nb))
     L = np.tril(rng.uniform(0.1, 0.2, (na, na)), -1) + np.diag(rng.uniform(1.0, 2.0, na))
     npair = nb * (nb + 1) // 2
-    ntile = (npair + 63) // 64
+    ntile = (npair + 127) // 128
     ri_bytes = 0
     for b in (na * nb * nb * 8, na * na * 8, na * npair * 8, na * npair * 8, na * na * 8,
               ntile * (ntile + 1) // 2 * 8, npair * npair * 8):  # host staging, X, B, G, tiles, eri
@@ -139,10 +139,12 @@ def test_ri_end_to_end_closed_forms(ctx):
     assert abs(eri[aa, bb] - J) < 1e-8
 
 
-@pytest.mark.parametrize("nb,na", [(1, 1), (2, 33), (11, 64), (12, 65)])
+@pytest.mark.parametrize("nb,na", [(1, 1), (2, 33), (11, 64), (12, 65), (20, 97), (5, 1024), (5, 1025)])
 def test_ri_edge_sizes(ctx, nb, na):
-    """Single pair / single auxiliary function, one-past-a-block sizes: random SPD factor and random
-    (ab|P) symmetric in a, b, compared with the oracle."""
+    """Single pair / single auxiliary function, one-past-a-block sizes, several 16-pair strips, and
+    the largest n_aux the one-launch substitution holds in LDS (1024) and the first beyond it (one
+    launch per block step): random SPD factor and random (ab|P) symmetric in a, b, compared with
+    the oracle."""
     rng = np.random.default_rng(nb * 100 + na)
     M = rng.normal(size=(na, na))
     L = np.linalg.cholesky(M @ M.T + na * np.eye(na))
