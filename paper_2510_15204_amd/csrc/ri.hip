@@ -44,28 +44,32 @@ constexpr int TR_ROWS = 32;  // rows of B per block step of the forward substitu
 // blocks, G_ik = L_ik D_k.  Then block step k is one product with the not-yet-solved rows X_k:
 //   B_k = G_kk X_k        and        X_i -= G_ik X_k for every block row i below k.
 
-// G_kk = D_k by substitution, row by row: lane j computes D[r][j] for every row r in turn (one block
-// per work-group of one wave); the rows solved so far stay in LDS.
+// G_kk = D_k by right-looking substitution on X = I in LDS: at step q row q is final once divided by
+// L[q][q], and every row below subtracts L[r][q] times it, all (r, j) in parallel.  Each entry sees
+// the same operations in the same order as the row-by-row forward substitution.  One 32 x 32 block
+// per work-group.
 __global__ __launch_bounds__(64) void ri_inv_kernel(const double* __restrict__ L, int na, double* __restrict__ G) {
-  __shared__ double Ld[TR_ROWS][TR_ROWS];
-  __shared__ double Dk[TR_ROWS][TR_ROWS + 1];
+  __shared__ double Ld[TR_ROWS][TR_ROWS + 1];
+  __shared__ double Xd[TR_ROWS][TR_ROWS + 1];
   const int r0 = blockIdx.x * TR_ROWS, nr = min(TR_ROWS, na - r0);
   const int tid = threadIdx.x;
   for (int e = tid; e < TR_ROWS * TR_ROWS; e += 64) {
     const int r = e / TR_ROWS, q = e - r * TR_ROWS;
     Ld[r][q] = (r < nr && q < nr) ? L[(int64_t)(r0 + r) * na + r0 + q] : (r == q ? 1.0 : 0.0);
+    Xd[r][q] = r == q ? 1.0 : 0.0;
   }
   __syncthreads();
-  const int j = tid & (TR_ROWS - 1);
-  for (int r = 0; r < TR_ROWS; ++r) {
-    double v = r == j ? 1.0 : 0.0;
-    for (int q = j; q < r; ++q) v -= Ld[r][q] * Dk[q][j];
-    if (tid < TR_ROWS) Dk[r][j] = v / Ld[r][r];
+  const int j = tid & (TR_ROWS - 1), h = tid / TR_ROWS;  // column; half of the rows below
+  for (int q = 0; q < TR_ROWS; ++q) {
+    if (tid < TR_ROWS) Xd[q][j] /= Ld[q][q];
+    __syncthreads();
+    const double xq = Xd[q][j];
+    for (int r = q + 1 + h; r < TR_ROWS; r += 2) Xd[r][j] -= Ld[r][q] * xq;
     __syncthreads();
   }
   for (int e = tid; e < TR_ROWS * TR_ROWS; e += 64) {
     const int r = e / TR_ROWS, q = e - r * TR_ROWS;
-    if (r < nr && q < nr) G[(int64_t)(r0 + r) * na + r0 + q] = q <= r ? Dk[r][q] : 0.0;
+    if (r < nr && q < nr) G[(int64_t)(r0 + r) * na + r0 + q] = q <= r ? Xd[r][q] : 0.0;
   }
 }
 
