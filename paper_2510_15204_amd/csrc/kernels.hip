@@ -943,12 +943,9 @@ static hipError_t launch_contract_t(const TaskDev* tasks, const TileDev* tiles, 
   constexpr int lds = ContractCfg<T, WM, WN, SC>::LDS_BYTES;
   static_assert(lds <= 160 * 1024, "LDS budget");
   const void* fn = sizeof(T) == 8 ? (const void*)contract_f64<WM, WN, SC> : (const void*)contract_mixed<WM, WN, SC>;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  // once per instantiation (a function-local static is initialised once, also with concurrent callers)
+  static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (attr != hipSuccess) return attr;
   if constexpr (sizeof(T) == 8)
     hipLaunchKernelGGL((contract_f64<WM, WN, SC>), dim3(ntiles), dim3(256), lds, st, tasks, tiles, ws);
   else
