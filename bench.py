@@ -89,8 +89,9 @@ def sample_elements(job, n_abp, rng):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this "
-                                   "build (see the sharding paragraph of the design document)",
+        print(json.dumps({"error": "this benchmark runs on one GPU: the library has no multi-GPU path "
+                                   "(whole grids would be spread over GPUs by their cost, each GPU running "
+                                   "the single-GPU path)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
