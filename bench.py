@@ -167,6 +167,11 @@ def main():
                 "frac": achieved / PEAK[prec], "traffic": traffic,
                 "kernel": ("contract_mixed" if prec == "mixed" else "contract_f64") + " (all launches)",
                 "flops_per_launch": flops, "mean_launch_ms": mean_contract_s * 1e3}
+    # what this device's matrix pipe sustains in the path's precision (a probe kernel of independent
+    # MFMAs, after the timed steps), beside the published peak that `frac` uses
+    probe = ctx.mfma_rate(prec) * 1e12
+    roofline["probe_peak"] = probe / 1e12
+    roofline["frac_of_probe"] = achieved / probe
     out = {"metric": "S/T/V/(ab|P) quadrature pair·points/s at stated error vs FP64; p99 job latency",
            "value": value, "unit": "pair·points/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True,

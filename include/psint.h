@@ -171,6 +171,13 @@ int32_t ps_plan_work(ps_ctx* ctx, const ps_job* job, double* pair_points, int64_
  * context when the job's inputs, the tiling and the budget are unchanged. */
 int32_t ps_set_tiling(ps_ctx* ctx, int32_t wm, int32_t wn, int32_t stage_chunks, int32_t ksplit);
 
+/* Measured matrix-pipe throughput of the context's device, for reading roofline fractions against
+ * what the chip sustains: a probe kernel in which every wave (16 per compute unit) issues long runs of
+ * independent 16x16x4 MFMAs (FP64 for PS_PREC_FP64, FP32 for PS_PREC_MIXED) on register operands;
+ * *tflops receives the best of three timed runs, in TFLOP/s (2048 FLOPs per MFMA).  Runs on the
+ * context's synchronous stream (about 10 ms of device time); PS_E_INVALID for other precisions. */
+int32_t ps_mfma_rate(ps_ctx* ctx, int32_t precision, double* tflops);
+
 /* ---- tile-shape autotuner ------------------------------------------------------------------- */
 typedef struct {
   int32_t wm, wn, stage_chunks, ksplit; /* as ps_set_tiling                                         */

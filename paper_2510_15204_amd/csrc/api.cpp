@@ -26,6 +26,7 @@ hipError_t launch_reduce(const TaskDev* tasks, const RedDev* reds, const int32_t
                          const double* ws, hipStream_t st);
 int contract_resident_workgroups(bool mixed, int wm, int wn, int sc);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+hipError_t launch_mfma_rate(bool fp64, int blocks, int iters, double* out, hipStream_t st);
 hipError_t launch_symmetrize(double* X, int n, hipStream_t st);
 hipError_t launch_cholesky(const double* A, double* L, int n, int* status, hipStream_t st);
 hipError_t launch_grid_points(const GridDev& G, const double* lines, const double* RA, double* xyzw, hipStream_t st);
@@ -560,6 +561,49 @@ int32_t ps_destroy(ps_ctx* ctx) {
   pool_destroy(ctx);
   delete ctx;
   return PS_OK;
+}
+
+int32_t ps_mfma_rate(ps_ctx* ctx, int32_t precision, double* tflops) {
+  if (!ctx) return PS_E_INVALID;
+  if (!tflops || (precision != PS_PREC_FP64 && precision != PS_PREC_MIXED)) {
+    ctx->err = "mfma_rate: tflops must be given, precision PS_PREC_FP64 or PS_PREC_MIXED";
+    return PS_E_INVALID;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
+  std::lock_guard<std::mutex> sync_guard(ctx->sync_mu);
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, ctx->device));
+  const int blocks = 4 * prop.multiProcessorCount;  // 16 waves per CU
+  const int iters = 4000;
+  const bool fp64 = precision == PS_PREC_FP64;
+  size_t got = 0;
+  double* out = (double*)pool_alloc(ctx, (size_t)blocks * 4 * sizeof(double), &got);
+  if (!out) {
+    ctx->err = "mfma_rate: no device memory for the probe's output";
+    return PS_E_NOMEM;
+  }
+  hipStream_t st = ctx->sync_slot.stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int32_t rc = PS_OK;
+  double best_ms = 0.0;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = PS_E_DEVICE;
+  for (int rep = 0; rep < 4 && rc == PS_OK; ++rep) {  // the first run is untimed
+    if (hipEventRecord(e0, st) != hipSuccess || launch_mfma_rate(fp64, blocks, iters, out, st) != hipSuccess ||
+        hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      rc = PS_E_DEVICE;
+      break;
+    }
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = PS_E_DEVICE;
+    if (rep > 0 && (best_ms == 0.0 || ms < best_ms)) best_ms = ms;
+  }
+  if (rc != PS_OK) ctx->err = std::string("mfma_rate: ") + hipGetErrorString(hipGetLastError());
+  (void)hipStreamSynchronize(st);
+  pool_release(ctx, out, got);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc == PS_OK) *tflops = (double)blocks * 4 * iters * 8 * 2048.0 / (best_ms * 1e-3) / 1e12;
+  return rc;
 }
 
 int32_t ps_set_tiling(ps_ctx* ctx, int32_t wm, int32_t wn, int32_t stage_chunks, int32_t ksplit) {

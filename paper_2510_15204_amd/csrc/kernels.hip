@@ -697,6 +697,37 @@ __global__ __launch_bounds__(256) void reduce_kernel(const TaskDev* __restrict__
   }
 }
 
+// Matrix-pipe throughput probe: every wave runs `iters` (a multiple of 16) rounds of 8 independent
+// 16 x 16 x 4 MFMAs (FP64, or FP32 inputs with FP32 sums) on register operands, and one sum per wave
+// is stored so that the work is kept.  2048 FLOPs per MFMA.
+template <typename T>
+__global__ __launch_bounds__(256) void mfma_rate_kernel(double* __restrict__ out, int iters) {
+  typedef typename std::conditional<sizeof(T) == 8, d4_t, f4_t>::type Acc;
+  const int lane = threadIdx.x & 63;
+  const T a = (T)(1.0 + 1e-3 * lane), b = (T)(1.0 - 1e-3 * lane);
+  Acc acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = Acc{};
+  // 16 rounds per loop trip: the accumulators stay in the matrix registers inside a trip
+  for (int i = 0; i < iters; i += 16) {
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if constexpr (sizeof(T) == 8)
+          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+        else
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
+      }
+  }
+  double sum = 0.0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sum += (double)acc[j][r];
+  if (lane == 0) out[blockIdx.x * 4 + (threadIdx.x >> 6)] = sum;
+}
+
 __global__ void fill_kernel(double* __restrict__ p, int64_t n, double v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -1006,6 +1037,15 @@ hipError_t launch_reduce(const TaskDev* tasks, const RedDev* reds, const int32_t
                          const double* ws, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   hipLaunchKernelGGL(reduce_kernel, dim3(nitems), dim3(256), 0, st, tasks, reds, items, ws);
+  return hipGetLastError();
+}
+
+// blocks x 256 threads; out holds 4 doubles per block
+hipError_t launch_mfma_rate(bool fp64, int blocks, int iters, double* out, hipStream_t st) {
+  if (fp64)
+    hipLaunchKernelGGL(mfma_rate_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, out, iters);
+  else
+    hipLaunchKernelGGL(mfma_rate_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, out, iters);
   return hipGetLastError();
 }
 

@@ -109,12 +109,14 @@ def lib():
         L.ps_autotune.argtypes = [vp, C.POINTER(Job), C.c_int32, C.POINTER(Tuning), C.POINTER(Tuning), C.c_int32,
                                   C.POINTER(C.c_int32)]
         L.ps_ri_assemble.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp, _dp]
+        L.ps_mfma_rate.argtypes = [vp, C.c_int32, _dp]
         L.ps_status_string.argtypes = [C.c_int32]
         L.ps_status_string.restype = C.c_char_p
         L.ps_last_error.argtypes = [vp]
         L.ps_last_error.restype = C.c_char_p
         for f in ("ps_create", "ps_destroy", "ps_compute", "ps_submit", "ps_wait", "ps_grid_points",
-                  "ps_eval_function", "ps_plan_work", "ps_set_tiling", "ps_autotune", "ps_ri_assemble"):
+                  "ps_eval_function", "ps_plan_work", "ps_set_tiling", "ps_autotune", "ps_ri_assemble",
+                  "ps_mfma_rate"):
             getattr(L, f).restype = C.c_int32
         _LIB = L
     return _LIB
@@ -135,7 +137,7 @@ def plan_work_host(job, precision=None):
 def exported_symbols():
     return ["ps_create", "ps_destroy", "ps_compute", "ps_submit", "ps_wait", "ps_grid_points",
             "ps_eval_function", "ps_plan_work", "ps_set_tiling", "ps_autotune", "ps_ri_assemble",
-            "ps_status_string", "ps_last_error"]
+            "ps_mfma_rate", "ps_status_string", "ps_last_error"]
 
 
 def _spec(s) -> GridSpec:
@@ -259,6 +261,13 @@ class Context:
         self._check(lib().ps_ri_assemble(self.h, nb, na, 1 if dev else 0, ptr(abP), ptr(L), ptr(B), ptr(eri),
                                          C.byref(ms)))
         return B, eri, ms.value
+
+    def mfma_rate(self, precision="fp64"):
+        """Measured matrix-pipe throughput of the device in TFLOP/s (ps_mfma_rate): FP64 MFMA for
+        "fp64", FP32 MFMA for "mixed"."""
+        t = C.c_double()
+        self._check(lib().ps_mfma_rate(self.h, PREC[precision], C.byref(t)))
+        return t.value
 
     def plan_work(self, job, precision=None):
         ref = _JobRef(job, precision)

@@ -419,3 +419,14 @@ def test_multi_pass_graph_replay_matches_eager_and_times_afresh():
     _say(f"{st0['n_passes']} passes, contraction ms over replays: {sorted(times)}")
     assert len(times) > 1  # measured on every replay
     c.close()
+
+
+@pytest.mark.parametrize("prec,peak", [("fp64", 78.6), ("mixed", 157.3)])
+def test_mfma_rate_probe(ctx, prec, peak):
+    """The matrix-pipe probe reports a rate between a third of the published dense peak and the peak
+    itself (plus 5% for rounding of the published figure and clock variation)."""
+    rate = ctx.mfma_rate(prec)
+    _say(f"{prec}: probe {rate:.1f} TFLOP/s of {peak} published")
+    assert peak / 3 < rate < 1.05 * peak
+    out = psint.C.c_double()
+    assert psint.lib().ps_mfma_rate(ctx.h, 7, psint.C.byref(out)) == psint.PS_E_INVALID
