@@ -1,0 +1,149 @@
+// Host check of the contraction plan (csrc/plan.cpp) on a job read from a text file: every output
+// element of every task is covered by exactly one reduction item, each item's K splits tile the
+// grid's point chunks [0, nchunks) in order without gaps or overlaps, every tile sits in one launch
+// whose tile shape holds it, the issued FLOPs add up, and the splits of one item are even.
+// Usage: plan_check <job file> <precision 0|1> <resident work-groups per launch> <budget GB>
+// Job file: natoms, atoms (x y z Z), nbf, basis rows (atom n l m zeta), naux, aux rows, grid spec
+// (n_mu n_nu n_phi q n_sp c1_scale c1_exp), npg, per-pair specs (A B + the 7 spec fields).
+#include <cstdio>
+#include <cstdlib>
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "plan.h"
+
+using namespace psint;
+
+static int fail(const char* what, long a = 0, long b = 0) {
+  printf("FAIL %s %ld %ld\n", what, a, b);
+  return 1;
+}
+
+int main(int argc, char** argv) {
+  if (argc < 5) return fail("usage");
+  FILE* f = fopen(argv[1], "r");
+  if (!f) return fail("open");
+  int na = 0;
+  if (fscanf(f, "%d", &na) != 1) return fail("read");
+  std::vector<ps_atom> atoms(na);
+  for (auto& a : atoms)
+    if (fscanf(f, "%lf %lf %lf %lf", &a.xyz[0], &a.xyz[1], &a.xyz[2], &a.Z) != 4) return fail("atom");
+  auto read_fns = [&](std::vector<ps_sto>& v) {
+    int n = 0;
+    if (fscanf(f, "%d", &n) != 1) return false;
+    v.resize(n);
+    for (auto& s : v)
+      if (fscanf(f, "%d %d %d %d %lf", &s.atom, &s.n, &s.l, &s.m, &s.zeta) != 5) return false;
+    return true;
+  };
+  std::vector<ps_sto> bf, ax;
+  if (!read_fns(bf) || !read_fns(ax)) return fail("functions");
+  ps_grid_spec sp;
+  if (fscanf(f, "%d %d %d %d %d %lf %lf", &sp.n_mu, &sp.n_nu, &sp.n_phi, &sp.q, &sp.n_sp, &sp.c1_scale,
+             &sp.c1_exp) != 7)
+    return fail("spec");
+  int npg = 0;
+  if (fscanf(f, "%d", &npg) != 1) npg = 0;
+  std::vector<ps_pair_grid> pgs(npg);
+  for (auto& g : pgs)
+    if (fscanf(f, "%d %d %d %d %d %d %d %lf %lf", &g.atom_a, &g.atom_b, &g.spec.n_mu, &g.spec.n_nu, &g.spec.n_phi,
+               &g.spec.q, &g.spec.n_sp, &g.spec.c1_scale, &g.spec.c1_exp) != 9)
+      return fail("pair spec");
+  fclose(f);
+  ps_job job{};
+  job.atoms = atoms.data();
+  job.n_atoms = na;
+  job.basis = bf.data();
+  job.n_bf = (int32_t)bf.size();
+  job.aux = ax.data();
+  job.n_aux = (int32_t)ax.size();
+  job.grid = sp;
+  job.pair_grids = pgs.data();
+  job.n_pair_grids = npg;
+  job.precision = atoi(argv[2]);
+  TileShape ts;  // the library's defaults: FP64 4 x 4 with 16-point stages, mixed 4 x 4 with 32
+  if (job.precision == PS_PREC_MIXED) ts.sc = 2;
+  const int slots = atoi(argv[3]);
+  ts.slots = ts.slots2 = ts.slots2n = slots;
+  for (int w = 1; w < 4; ++w) ts.slots_n[w] = slots;
+  const size_t budget = (size_t)(atof(argv[4]) * 1e9);
+  Plan p;
+  std::string err;
+  if (build_plan(&job, ts, 0, budget, &p, &err) != PS_OK) {
+    printf("FAIL plan %s\n", err.c_str());
+    return 1;
+  }
+
+  // tiles by (pass, partial-tile offset): each pass reuses the workspace, each offset once per pass
+  std::vector<int> pass_of_tile(p.tiles.size(), -1), pass_of_red(p.reds.size(), -1);
+  for (int k = 0; k < (int)p.passes.size(); ++k) {
+    for (int i = p.passes[k].tile0; i < p.passes[k].tile1; ++i) pass_of_tile[i] = k;
+    for (const auto& ph : p.passes[k].red_by_phase)
+      for (int r : ph) pass_of_red[r] = k;
+  }
+  std::map<std::pair<int, int64_t>, int> tile_at;
+  for (int i = 0; i < (int)p.tiles.size(); ++i) {
+    if (pass_of_tile[i] < 0) return fail("tile in no pass", i);
+    if (!tile_at.emplace(std::make_pair(pass_of_tile[i], p.tiles[i].ws), i).second)
+      return fail("two tiles of a pass share a partial tile", i);
+  }
+  for (size_t r = 0; r < p.reds.size(); ++r)
+    if (pass_of_red[r] < 0) return fail("item reduced in no pass", (long)r);
+  // launch of each tile, and the launch's shape holds the tile
+  std::vector<int> launch_of(p.tiles.size(), -1);
+  for (const Pass& ps : p.passes)
+    for (const auto& l : ps.launches)
+      for (int i = l.tile0; i < l.tile1; ++i) {
+        if (launch_of[i] >= 0) return fail("tile in two launches", i);
+        launch_of[i] = l.shape.wm * 10 + l.shape.wn;
+        const TileDev& t = p.tiles[i];
+        if (t.nrows > l.shape.bm() || t.np > l.shape.bn()) return fail("tile larger than its shape", i);
+        if (t.nu + t.nv > l.shape.maxuv()) return fail("staged columns beyond the shape", i);
+      }
+  for (size_t i = 0; i < p.tiles.size(); ++i)
+    if (launch_of[i] < 0) return fail("tile in no launch", (long)i);
+
+  // reduction items: splits tile [0, nchunks) in order, evenly; items cover each task once
+  std::vector<std::vector<unsigned char>> cover(p.tasks.size());  // per task: row x column hits
+  for (size_t t = 0; t < p.tasks.size(); ++t) cover[t].assign((size_t)p.tasks[t].dev.npairs * p.tasks[t].dev.ny, 0);
+  std::vector<char> tile_used(p.tiles.size(), 0);
+  double issued = 0.0;
+  for (size_t r = 0; r < p.reds.size(); ++r) {
+    const RedDev& R = p.reds[r];
+    const TaskHost& th = p.tasks[R.task];
+    const int64_t nch = p.grids[th.grid].dev.npad / KC;
+    int64_t next = 0, lo = 1 << 30, hi = 0;
+    for (int s = 0; s < R.nsplit; ++s) {
+      auto it = tile_at.find(std::make_pair(pass_of_red[r], R.ws + (int64_t)s * R.bm * R.bn));
+      if (it == tile_at.end()) return fail("split without a tile", (long)r, s);
+      const TileDev& t = p.tiles[it->second];
+      tile_used[it->second] = 1;
+      if (t.task != R.task || t.row0 != R.row0 || t.nrows != R.nrows || t.p0 != R.p0 || t.np != R.np)
+        return fail("split of another item", (long)r, s);
+      if (t.kc0 != next || t.nkc <= 0 || t.nkc % TileShape::SC_MAX) return fail("split range", (long)r, s);
+      next += t.nkc;
+      lo = std::min<int64_t>(lo, t.nkc);
+      hi = std::max<int64_t>(hi, t.nkc);
+      issued += 2.0 * R.bm * R.bn * t.nkc * KC;
+    }
+    if (next != nch) return fail("splits do not end at the grid's last chunk", (long)r, (long)next);
+    if (hi - lo > 2 * TileShape::SC_MAX) return fail("uneven splits", (long)r, (long)(hi - lo));
+    auto& cv = cover[R.task];
+    const int ny = p.tasks[R.task].dev.ny;
+    if (R.row0 < 0 || R.row0 + R.nrows > p.tasks[R.task].dev.npairs || R.p0 < 0 || R.p0 + R.np > ny)
+      return fail("item outside its task", (long)r);
+    for (int i = 0; i < R.nrows; ++i)
+      for (int c = 0; c < R.np; ++c)
+        if (cv[(size_t)(R.row0 + i) * ny + R.p0 + c]++) return fail("element in two items", R.task, R.row0 + i);
+  }
+  for (size_t i = 0; i < p.tiles.size(); ++i)
+    if (!tile_used[i]) return fail("tile of no item", (long)i);
+  for (size_t t = 0; t < p.tasks.size(); ++t)
+    for (size_t e = 0; e < cover[t].size(); ++e)
+      if (cover[t][e] != 1) return fail("element of no item", (long)t, (long)e);
+  if (issued != p.issued_flops) return fail("issued FLOPs", (long)(issued / 1e9), (long)(p.issued_flops / 1e9));
+  printf("ok %zu tiles %zu items %zu passes\n", p.tiles.size(), p.reds.size(), p.passes.size());
+  return 0;
+}

@@ -1,0 +1,53 @@
+"""CPU: invariants of the contraction plan (csrc/plan.cpp, built here with g++ into
+tests/plan_check.cpp) on the benchmark workloads and under a small memory budget: every output
+element of every task is covered by exactly one reduction item, each item's K splits tile its grid's
+point chunks in order and evenly, every tile sits in a launch whose shape holds it, and the issued
+FLOPs add up."""
+import os
+import subprocess
+
+import pytest
+
+from paper_2510_15204_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def checker(tmp_path_factory):
+    d = tmp_path_factory.mktemp("plan_check")
+    exe = str(d / "plan_check")
+    csrc = os.path.join(ROOT, "paper_2510_15204_amd", "csrc")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-Wall", "-I", csrc, os.path.join(ROOT, "tests", "plan_check.cpp"),
+                    os.path.join(csrc, "plan.cpp"), "-o", exe], check=True)
+    return exe, d
+
+
+def _write_job(job, path):
+    lines = [str(job.n_atoms)]
+    lines += [" ".join(repr(float(v)) for v in (*x, z)) for x, z in zip(job.xyz, job.Z)]
+    for fns in (job.basis, job.aux):
+        lines.append(str(len(fns)))
+        lines += [f"{int(r[0])} {int(r[1])} {int(r[2])} {int(r[3])} {float(r[4])!r}" for r in fns]
+    lines.append(" ".join(str(v) for v in job.grid.as_tuple()))
+    lines.append(str(len(job.pair_grids)))
+    lines += [f"{a} {b} " + " ".join(str(v) for v in s.as_tuple()) for (a, b), s in job.pair_grids.items()]
+    path.write_text("\n".join(lines) + "\n")
+
+
+@pytest.mark.parametrize("name,prec,budget_gb", [
+    ("diatomic_small", 0, 200.0),
+    ("triatomic_qz", 0, 200.0),
+    ("triatomic_qz", 1, 200.0),
+    ("triatomic_qz", 0, 7.0),       # one grid per memory pass, small workspace reservations
+    ("hydrocarbon9", 0, 246.0),     # 252 uneven grids, three passes
+    ("hydrocarbon9", 1, 246.0),
+])
+def test_plan_invariants(checker, name, prec, budget_gb):
+    exe, d = checker
+    job = getattr(W, name)()
+    f = d / f"{name}.txt"
+    _write_job(job, f)
+    out = subprocess.run([exe, str(f), str(prec), "512", str(budget_gb)], capture_output=True, text=True, timeout=300)
+    print(out.stdout.strip())
+    assert out.returncode == 0 and out.stdout.startswith("ok"), out.stdout + out.stderr
