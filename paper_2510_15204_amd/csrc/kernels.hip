@@ -12,6 +12,8 @@
 //   reduce_kernel    sums the partial tiles of a tile in split order (deterministic) and scatters
 //                    into the FP64 output buffer, with an optional mirrored write.
 //   symmetrize / cholesky / fill / copy helpers.
+//   mfma_rate_kernel a probe of the matrix pipe's sustained FP64 / FP32 rate (independent MFMAs on
+//                    register operands), for reading roofline fractions.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
