@@ -123,6 +123,26 @@ def test_ri_scratch_shares_the_context_budget(ctx, oracle_inputs):
         assert np.array_equal(x, y)
 
 
+def test_ri_between_repeats_keeps_the_replay(oracle_inputs):
+    """With memory to spare, an RI call between two runs of the same job leaves the job's arena,
+    plan and captured graphs alone: the third run is a graph replay and all results are unchanged."""
+    job, ref, _, _ = oracle_inputs
+    c = psint.Context(0)
+    try:
+        out1, st1, _ = c.compute(job)
+        out2, st2, _ = c.compute(job)
+        B, eri, _ = c.ri_assemble(out2["abP"], out2["PQ_chol"])
+        out3, st3, _ = c.compute(job)
+        B2, eri2, _ = c.ri_assemble(out3["abP"], out3["PQ_chol"])
+    finally:
+        c.close()
+    assert st1["graph_replay"] == 0 and st2["graph_replay"] == 1 and st3["graph_replay"] == 1
+    for k in ("S", "T", "V", "PQ", "PQ_chol", "abP"):
+        assert np.array_equal(out2[k], out1[k]) and np.array_equal(out3[k], out1[k])
+    assert np.array_equal(B2, B) and np.array_equal(eri2, eri)
+    assert np.max(np.abs(out1["abP"] - ref["abP"])) < 1e-10
+
+
 def test_ri_end_to_end_closed_forms(ctx):
     """GPU quadrature + GPU Cholesky + GPU RI on 1s(zeta = 1) atoms with 1s(2) auxiliaries: the
     densities lie in the auxiliary span, so (aa|aa) = 5/8 and (aa|bb) = J(R) exactly (up to the grid)."""
