@@ -24,17 +24,17 @@ namespace psint {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void ri_gather_kernel(const double* __restrict__ abP, int nb, int na,
+// (ab|P) [P][a][b] -> A[P][a(a+1)/2 + b] for b <= a: one wave per row a of one P (blockIdx.y), lanes
+// over b, so reads and writes are contiguous runs and no index is divided.
+__global__ __launch_bounds__(256) void ri_gather_kernel(const double* __restrict__ abP, int nb,
                                                         double* __restrict__ A) {
+  const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (a >= nb) return;
+  const int64_t P = blockIdx.y;
   const int64_t npair = (int64_t)nb * (nb + 1) / 2;
-  const int64_t total = (int64_t)na * nb * nb;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t P = e / ((int64_t)nb * nb);
-    const int rem = (int)(e - P * nb * nb);
-    const int a = rem / nb, b = rem - a * nb;
-    if (b > a) continue;
-    A[P * npair + (int64_t)a * (a + 1) / 2 + b] = abP[e];
-  }
+  const double* __restrict__ src = abP + (P * nb + a) * nb;
+  double* __restrict__ dst = A + P * npair + (int64_t)a * (a + 1) / 2;
+  for (int b = threadIdx.x & 63; b <= a; b += 64) dst[b] = src[b];
 }
 
 constexpr int TR_ROWS = 32;  // rows of B per block step of the forward substitution
@@ -448,12 +448,9 @@ extern "C" int32_t ps_ri_assemble(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, int3
   RI_TRY(hipEventCreate(&e0));
   RI_TRY(hipEventCreate(&e1));
   RI_TRY(hipEventRecord(e0, st));
-  {
-    int64_t blocks = (na * nb * nb + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(ri_gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d_abp, n_bf, n_aux, d_x);
-    RI_TRY(hipGetLastError());
-  }
+  hipLaunchKernelGGL(ri_gather_kernel, dim3((unsigned)((n_bf + 3) / 4), (unsigned)n_aux), dim3(256), 0, st, d_abp,
+                     n_bf, d_x);
+  RI_TRY(hipGetLastError());
   // blocked forward substitution on the transformed factor, B into its own buffer
   {
     const int nblk = (n_aux + TR_ROWS - 1) / TR_ROWS;
