@@ -52,6 +52,7 @@ def lib():
         L.orc_cholesky.argtypes = [C.c_int32, _dp, _dp]
         L.orc_grid_list.argtypes = [C.POINTER(_Job), _ip, C.c_int64]
         L.orc_grid_list.restype = C.c_int64
+        L.orc_route.argtypes = [C.POINTER(_Job), C.c_int32, C.c_int32, C.c_int32, C.c_int32, _ip, C.c_int32]
         L.orc_set_threads.argtypes = [C.c_int32]
         L.orc_set_threads.restype = C.c_int32
         _LIB = L
@@ -166,6 +167,17 @@ def grid_list(job):
     abc = np.zeros((n, 3), dtype=np.int32)
     lib().orc_grid_list(C.byref(ref.s), _i(abc), n)
     return [tuple(int(v) for v in r) for r in abc]
+
+
+def route(job, kind, i, j, k=0):
+    """Contributions of one element: list of ((A, B, C), nuclei) with C = -1 for an unrefined grid."""
+    ref = _JobRef(job)
+    cap = 2 + ref.xyz.shape[0]
+    out = np.zeros((cap, 6), dtype=np.int32)
+    n = lib().orc_route(C.byref(ref.s), int(kind), int(i), int(j), int(k), _i(out), cap)
+    if n < 0:
+        raise ValueError(f"route rc={n}")
+    return [((int(r[0]), int(r[1]), int(r[2])), tuple(int(v) for v in r[4:4 + r[3]])) for r in out[:n]]
 
 
 def compute_elements(job, kinds, i, j, k=None):

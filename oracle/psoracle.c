@@ -546,6 +546,28 @@ static int route(const orc_job* J, int kind, int i, int j, int k, contrib* out) 
   }
 }
 
+int orc_route(const orc_job* J, int32_t kind, int32_t i, int32_t j, int32_t k, int32_t* out,
+              int32_t cap) {
+  if (!J || kind < ORC_S || kind > ORC_ABP) return -1;
+  int nmax1 = (kind == ORC_PQ) ? J->n_aux : J->n_bf;
+  if (i < 0 || i >= nmax1 || j < 0 || j >= nmax1) return -1;
+  if (kind == ORC_ABP && (k < 0 || k >= J->n_aux)) return -1;
+  contrib* cb = (contrib*)malloc(sizeof(contrib) * (size_t)(2 + J->n_atoms));
+  if (!cb) return -3;
+  int n = route(J, kind, i, j, k, cb);
+  for (int c = 0; c < n && c < cap; ++c) {
+    int32_t* o = out + 6 * c;
+    o[0] = cb[c].g.A;
+    o[1] = cb[c].g.B;
+    o[2] = cb[c].g.C;
+    o[3] = cb[c].n_nuc;
+    o[4] = cb[c].n_nuc > 0 ? cb[c].nuc[0] : -1;
+    o[5] = cb[c].n_nuc > 1 ? cb[c].nuc[1] : -1;
+  }
+  free(cb);
+  return n;
+}
+
 static const double* spec_for(const orc_job* J, int A, int B) {
   for (int p = 0; p < J->n_pair_specs; ++p) {
     int a = J->pair_ab[2 * p], b = J->pair_ab[2 * p + 1];

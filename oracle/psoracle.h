@@ -16,6 +16,11 @@
  *   - Coulomb 3-index integrals through the potential of an auxiliary STO: eqs. 15-16
  *   - RI metric used with its inverse: eq. 14
  *
+ * Pins: closed forms, library routines and an independent 2-D quadrature fix every one- and
+ * two-centre value and the three-centre values of collinear atoms.  Three-centre values with the
+ * third centre off the pair axis have no closed form: they are pinned only through the point-charge
+ * limit of (ab|P) and by grid self-convergence.
+ *
  * Units: bohr, hartree.  Functions are passed as rows (atom, n, l, m, zeta) of doubles.
  * All functions return 0 on success and a negative code on invalid input.
  */
@@ -83,6 +88,12 @@ int orc_cholesky(int32_t n, const double* A, double* L);
 
 /* Grid routing (exposed for pins): list of grids of the job, as (A, B, C) triples.  Returns count. */
 int64_t orc_grid_list(const orc_job* job, int32_t* abc, int64_t cap);
+
+/* Routing of one element (exposed for pins): its contributions as rows (A, B, C, n_nuc, nuc0, nuc1)
+ * -- the grid G(A,B|C) (C = -1: unrefined) it is summed on and, for V, the nuclei whose attraction is
+ * summed there.  Writes at most cap rows; returns the number of contributions. */
+int orc_route(const orc_job* job, int32_t kind, int32_t i, int32_t j, int32_t k, int32_t* out,
+              int32_t cap);
 
 /* OpenMP thread count (0 = leave the runtime default).  Returns the count in use. */
 int32_t orc_set_threads(int32_t n);

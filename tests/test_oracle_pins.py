@@ -74,6 +74,25 @@ def test_weights_sum_to_spheroid_volume(C):
     assert abs(w.sum() / vol - 1) < 1e-12
 
 
+@pytest.mark.parametrize("cells,zeta", [((10, 10, 4), 0.5), ((14, 12, 4), 0.5)])
+def test_norm_deficit_is_mass_outside_outermost_mu_line(cells, zeta):
+    """Where the outermost mu line lies (eqs. 7, 12, 17 with a = half the H-H distance in bohr):
+    a normalised diffuse 1s function on one focus loses, on the grid, exactly its mass outside the
+    spheroid mu <= mu_max, i.e. 1 - S_aa equals that exterior mass (here 1e-2 and 5e-4), computed by an
+    independent 2-D quadrature over xi > cosh(mu_max).  A 1% error in mu_max changes the exterior mass
+    by about 30%; the interior quadrature error is below 1e-3 of it."""
+    a = 0.7
+    xyz = np.array([[0.0, 0.0, a], [0.0, 0.0, -a]])
+    n_mu = cells[0]
+    mu_max = 2.3 * a ** 0.25 * math.atanh(n_mu / (n_mu + 1))
+    ext = integrate.dblquad(
+        lambda eta, xi: zeta ** 3 / PI * math.exp(-2 * zeta * a * (xi - eta)) * (xi * xi - eta * eta),
+        math.cosh(mu_max), math.cosh(mu_max) + 80, -1, 1, epsabs=1e-15, epsrel=1e-12)[0] * 2 * PI * a ** 3
+    r = O.compute_full(MiniJob(xyz, [1, 1], [[0, 1, 0, 0, zeta]], [[0, 1, 0, 0, 2.0]], Spec(*cells)),
+                       want=("S",))
+    assert abs((1 - r["S"][0, 0]) / ext - 1) < 2e-3
+
+
 @pytest.mark.parametrize("C,nsp,q", [(-1, 3, 3), (0, 3, 3), (0, 2, 4)])
 def test_polynomial_exactness_per_axis(C, nsp, q):
     """sum_g (w_g / J_g) p(mu,nu,phi) is exact for degree <= 2Q-1 per axis over the coordinate box."""
@@ -417,6 +436,200 @@ def test_three_centre_grid_moved_singularity():
     aC = R / 2
     ref = ref_integral([Fn("A", 1, 0, 0, zeta_a), Fn("A", 1, 0, 0, zeta_a), Fn("B", 2, 0, 0, 1.7, "pot")], aC)
     assert abs(got - ref) < 2e-6 * abs(ref)
+
+
+# ---------------------------------------------------------------------------------------------
+# Three or more atoms through compute_full: routing of blocks to the grids G(A,B|C) (Section 4:
+# polyatomics from 3-atom subsets; Sections 2.2-2.3: third-centre grids; eqs. 15-16)
+# ---------------------------------------------------------------------------------------------
+
+QUAD = np.array([[0.0, 0.0, 0.0], [1.9, 0.0, 0.4], [-0.6, 1.7, -0.3], [0.5, -0.8, 1.8]])  # not planar
+QUAD_Z = [1.0, 2.0, 1.5, 0.5]
+QUAD_ZETA = [1.3, 0.9, 1.6, 1.1]
+QUAD_AUX = [2.2, 1.8, 2.6, 2.0]
+
+
+@pytest.mark.parametrize("natoms", [3, 4])
+def test_routing_closed_forms_polyatomic(natoms):
+    """1s functions on every atom of a bent triatomic and of a non-planar four-atom molecule.
+
+    Every element checked here has at most two centres, so it has an exact value whatever grid it is
+    summed on, and a dropped, doubled or misassigned contribution of the routing shows at once:
+      - V_aa = -Z_A zeta - sum_{C != A} Z_C [1/R - (zeta + 1/R) e^{-2 zeta R}] (every nucleus once);
+      - S_aa = 1, T_aa = zeta^2 / 2;
+      - S_ab, T_ab, (ab|P on A or B), (aa|P on C), (P|Q): spherical functions, so each equals the
+        independent 2-D elliptic-coordinate quadrature with the two centres on the z axis.
+    Tolerance 1e-9: the (28,28,12)-cell grids' own error for these exponents is <= 3.3e-10."""
+    xyz = QUAD[:natoms] if natoms == 4 else TRI
+    Z = QUAD_Z[:natoms]
+    zeta = QUAD_ZETA[:natoms]
+    azeta = QUAD_AUX[:natoms]
+    basis = [[X, 1, 0, 0, zeta[X]] for X in range(natoms)]
+    aux = [[X, 1, 0, 0, azeta[X]] for X in range(natoms)]
+    r = O.compute_full(MiniJob(xyz, Z, basis, aux, Spec(28, 28, 12)), want=("S", "T", "V", "PQ", "abP"))
+    tol = 1e-9
+    dist = lambda X, Y: float(np.linalg.norm(xyz[X] - xyz[Y]))
+    for A in range(natoms):
+        z = zeta[A]
+        ref = -Z[A] * z
+        for C in range(natoms):
+            if C != A:
+                R = dist(A, C)
+                ref -= Z[C] * (1 / R - (z + 1 / R) * math.exp(-2 * z * R))
+        assert abs(r["V"][A, A] - ref) < tol, A
+        assert abs(r["S"][A, A] - 1) < tol and abs(r["T"][A, A] - z * z / 2) < tol, A
+        for C in range(natoms):
+            cen = "A" if C == A else "B"
+            half = 0.5 * dist(A, C) if C != A else 1.0
+            ref = ref_integral([Fn("A", 1, 0, 0, z), Fn("A", 1, 0, 0, z), Fn(cen, 1, 0, 0, azeta[C], "pot")], half)
+            assert abs(r["abP"][C, A, A] - ref) < tol, (A, C)
+    for A in range(natoms):
+        for B in range(A + 1, natoms):
+            a = 0.5 * dist(A, B)
+            fa, fb = Fn("A", 1, 0, 0, zeta[A]), Fn("B", 1, 0, 0, zeta[B])
+            assert abs(r["S"][A, B] - ref_integral([fa, fb], a)) < tol, (A, B)
+            T = 0.5 * (ref_integral([fa, Fn("B", 1, 0, 0, zeta[B], "kin")], a)
+                       + ref_integral([Fn("A", 1, 0, 0, zeta[A], "kin"), fb], a))
+            assert abs(r["T"][A, B] - T) < tol, (A, B)
+            for P, cen in ((A, "A"), (B, "B")):
+                ref = ref_integral([fa, fb, Fn(cen, 1, 0, 0, azeta[P], "pot")], a)
+                assert abs(r["abP"][P, A, B] - ref) < tol, (A, B, P)
+            pq = 0.5 * (ref_integral([Fn("A", 1, 0, 0, azeta[A], "pot"), Fn("B", 1, 0, 0, azeta[B])], a)
+                        + ref_integral([Fn("B", 1, 0, 0, azeta[B], "pot"), Fn("A", 1, 0, 0, azeta[A])], a))
+            assert abs(r["PQ"][A, B] - pq) < tol, (A, B)
+
+
+def test_routing_structure_five_atoms():
+    """Where every element of a five-atom molecule is summed, against what the method requires.
+
+    - V_ab sums the attraction of every nucleus exactly once (its definition).
+    - A grid G(A,B|C) integrates products of functions on A and B (Section 2.1): the atoms of the
+      element's basis (or auxiliary) functions are foci of every grid it is summed on (both foci when
+      the two atoms differ).
+    - A nucleus or auxiliary potential centred on a third atom is singular there (eqs. 15-16), and the
+      paper sums such terms on the grid refined at that atom (Section 2.2): its centre is either a focus
+      or the third centre C of the grid, with both of C's lines moved onto it (the atoms are placed
+      off every pair axis, so the split applies)."""
+    xyz = np.array([[0.0, 0.0, 0.0], [1.9, 0.2, 0.3], [-0.5, 1.8, -0.4], [0.6, -0.9, 1.9], [1.5, 1.6, 1.4]])
+    Z = [1.0, 2.0, 3.0, 4.0, 5.0]
+    basis = [[X, 1, 0, 0, 1.0 + 0.1 * X] for X in range(5)]
+    aux = [[X, 1, 0, 0, 2.0 + 0.1 * X] for X in range(5)]
+    j = MiniJob(xyz, Z, basis, aux, Spec(6, 6, 4))
+    spec = Spec(6, 6, 4).as_tuple()
+    refined = {}
+
+    def check_centre(grid, X):
+        A, B, C = grid
+        if X in (A, B):
+            return
+        assert X == C, (grid, X)
+        if grid not in refined:
+            info = O.grid_info(xyz, A, B, C, spec)
+            refined[grid] = info["moved_mu"] and info["moved_nu"] and info["split"]
+        assert refined[grid], grid
+
+    def check_foci(grid, X, Y):
+        A, B, _ = grid
+        assert X in (A, B) and Y in (A, B), (grid, X, Y)
+
+    for kind, nfun, centre in ((O.S, 5, basis), (O.T, 5, basis), (O.PQ, 5, aux)):
+        for a in range(nfun):
+            for b in range(nfun):
+                con = O.route(j, kind, a, b)
+                assert len(con) == 1 and con[0][1] == ()
+                check_foci(con[0][0], centre[a][0], centre[b][0])
+    for a in range(5):
+        for b in range(5):
+            con = O.route(j, O.V, a, b)
+            nuclei = sorted(n for _, nuc in con for n in nuc)
+            assert nuclei == list(range(5)), (a, b, con)
+            for grid, nuc in con:
+                check_foci(grid, basis[a][0], basis[b][0])
+                for n in nuc:
+                    check_centre(grid, n)
+            for P in range(5):
+                con = O.route(j, O.ABP, a, b, P)
+                assert len(con) == 1 and con[0][1] == ()
+                check_foci(con[0][0], basis[a][0], basis[b][0])
+                check_centre(con[0][0], aux[P][0])
+
+
+LINE_Z = [2.4, 0.6, -1.2]
+
+
+def test_collinear_three_centre_values():
+    """Three atoms on the z axis: every function with its azimuth about the common axis, so the
+    three-centre values ((ab|P on C) on G(A,B|C), and V_ab with the nucleus C summed there) have an
+    independent reference, the elliptic-coordinate quadrature with the third centre at a break point.
+    Grid errors on the (32,32,16)-cell grids: (ab|P) <= 1.4e-10; V <= 6.3e-6, from a nucleus on the
+    axis at a cell corner (the third-centre line moves in mu only, since the centre lies on the fixed
+    nu = 0 or pi line, Section 2.3), converging as h^2.  A dropped or misassigned contribution is
+    O(0.1) here."""
+    xyz = np.array([[0.0, 0.0, z] for z in LINE_Z])
+    Z = [1.0, 2.0, 1.5]
+    basis = [[0, 2, 1, 0, 1.3], [0, 2, 1, 1, 1.2], [1, 1, 0, 0, 1.1], [1, 3, 2, 1, 0.9], [2, 1, 0, 0, 1.4]]
+    aux = [[2, 2, 1, 0, 1.7], [2, 3, 2, 1, 2.1], [0, 1, 0, 0, 2.0]]
+    r = O.compute_full(MiniJob(xyz, Z, basis, aux, Spec(32, 32, 16)), want=("V", "abP"))
+    for (i, j) in [(0, 2), (1, 3), (2, 4), (0, 4)]:
+        Ai, Aj = int(basis[i][0]), int(basis[j][0])
+        mid = 0.5 * (LINE_Z[Ai] + LINE_Z[Aj])
+        a = 0.5 * abs(LINE_Z[Ai] - LINE_Z[Aj])
+        fi = Fn(LINE_Z[Ai] - mid, *basis[i][1:])
+        fj = Fn(LINE_Z[Aj] - mid, *basis[j][1:])
+        V = -sum(Z[C] * ref_integral([fi, fj, Fn(LINE_Z[C] - mid, 1, 0, 0, 1.0, "rinv")], a) for C in range(3))
+        assert abs(r["V"][i, j] - V) < 2e-5, (i, j)
+        for P, f in enumerate(aux):
+            ref = ref_integral([fi, fj, Fn(LINE_Z[int(f[0])] - mid, *f[1:], kind="pot")], a)
+            assert abs(r["abP"][P, i, j] - ref) < 1e-9, (i, j, P)
+            assert abs(r["abP"][P, j, i] - ref) < 1e-9, (i, j, P)
+
+
+@pytest.mark.parametrize("natoms", [3, 4])
+def test_point_charge_limit_of_three_centre_coulomb(natoms):
+    """(ab|P on C) / q_P -> <a|1/r_C|b> as the 1s auxiliary function on C tightens (eqs. 15-16).
+
+    For a 1s charge of exponent z the potential is q/r [1 - (1 + z r/2) e^{-z r}], so with
+    K(s) = (1 + z s/2) e^{-z s} / s and a density rho = chi_a chi_b smooth at C,
+        D(z) = (ab|P)/q_P - <a|1/r_C|b> = -int rho K = -8 pi rho(C)/z^2 - 12 pi lap rho(C)/z^4 + O(z^-6).
+    <a|1/r_C|b> is read from V_ab with Z_A = Z_B = 0, Z_C = 1; both sums run on G(A,B|C) with its
+    refinement at C (bent triatomic, C off the A-B axis).  rho(C) and lap rho(C) come from the 1s closed
+    form (finite differences for the Laplacian).  The first two terms must account for D to within 10%
+    of the second one at z = 8 and 16 (measured 2-3%), and the relative size of the remainder beyond
+    the first term must shrink about 4x per doubling of z.  With four atoms a fourth atom D (no charge,
+    no functions) is nearer the A-B midpoint than C, so the pair grid of (A,B) is G(A,B|D) and only
+    G(A,B|C) is refined at C: the block must be summed there."""
+    za, zb = 1.2, 1.0
+    spec = Spec(32, 32, 16, 4, 4)
+    xyz = TRI if natoms == 3 else np.vstack([TRI, [[0.709, 1.2, 0.554]]])
+    charges = [0.0, 0.0, 1.0] + [0.0] * (natoms - 3)
+
+    def chi1s(z, c, p):
+        rr = np.linalg.norm(p - c, axis=-1)
+        return (2 * z) ** 1.5 / math.sqrt(2) * np.exp(-z * rr) / math.sqrt(4 * PI)
+
+    def rho(p):
+        return chi1s(za, TRI[0], p) * chi1s(zb, TRI[1], p)
+
+    RC = TRI[2]
+    rhoC = float(rho(RC[None])[0])
+    h = 1e-3
+    lap = 0.0
+    for d in range(3):
+        e = np.zeros(3)
+        e[d] = h
+        v = [float(rho((RC + k * e)[None])[0]) for k in (-2, -1, 0, 1, 2)]
+        lap += (-v[0] + 16 * v[1] - 30 * v[2] + 16 * v[3] - v[4]) / (12 * h * h)
+    rel = []
+    for zp in (8.0, 16.0):
+        j = MiniJob(xyz, charges, [[0, 1, 0, 0, za], [1, 1, 0, 0, zb]], [[2, 1, 0, 0, zp]], spec)
+        r = O.compute_full(j, want=("V", "abP"))
+        q = 8 * math.sqrt(PI) * zp ** -1.5
+        D = r["abP"][0, 0, 1] / q + r["V"][0, 1]
+        lead = -8 * PI * rhoC / zp ** 2
+        nxt = -12 * PI * lap / zp ** 4
+        assert abs(D - lead - nxt) < 0.1 * abs(nxt), zp
+        rel.append(abs(D / lead - 1))
+    assert 3.0 < rel[0] / rel[1] < 5.0
 
 
 def test_grid_convergence_rmse_decreases():
