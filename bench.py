@@ -3,17 +3,20 @@
 
 One step = one ps_compute of the whole job (grid generation, function and potential evaluation,
 every contraction, reductions, symmetrisation and the (P|Q) Cholesky) with outputs left in HBM.
-The workload is the bent triatomic with the quadruple-zeta-sized basis on three refined
-96x96x48-point grids in FP64 (--workload picks another).  Prints one JSON line.
+The default workload is the largest single-GPU configuration: the 9-atom hydrocarbon with the
+quadruple-zeta-sized basis on its 252 grids G(A,B|C) of 64-128 points per axis (uneven blocks,
+several memory passes), in FP64 (--workload and --precision pick others).  Prints one JSON line.
 
+  latency_ms    p50 / p99 / max of the timed steps and every step's time.
   roofline      the contraction kernel (the dominant kernel): algorithmic FLOPs per launch
                 (2 per pair-point) over the launch's mean duration, measured with HIP events the
                 library records around it on its own stream, against the MI355X FP64 (or FP32 for
                 the mixed path) dense peak.
-  cpu_baseline  the FP64 CPU oracle timed on a seeded sample of the same job's output elements;
-                the same sample gives the stated max-abs error of the GPU outputs.
-  error_vs_fp64_full  (mixed precision) max-abs error of every output element against an FP64
-                run of the same job, absolute and over the type's largest element.
+  mixed         (FP64 runs) the same job in mixed precision after the timed steps: throughput,
+                contraction rate and the max-abs error of every output element against the FP64 run.
+  cpu_baseline  the FP64 CPU oracle timed on a seeded sample of elements confined to a few of the
+                job's grids, all host cores and one core; the same sample gives the stated max-abs
+                error of the GPU outputs against the oracle.
 """
 import argparse
 import json
@@ -34,7 +37,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="triatomic_qz",
+    ap.add_argument("--workload", default="hydrocarbon9",
                     choices=["triatomic_qz", "triatomic_5z", "diatomic_small", "hydrocarbon9", "serving_stream",
                              "grid_ladder", "nsp_sweep", "geometry_scan"])
     ap.add_argument("--autotune", action="store_true",
@@ -42,9 +45,12 @@ def parse():
     ap.add_argument("--requests", type=int, default=40, help="serving_stream: measured requests")
     ap.add_argument("--warmup-requests", type=int, default=3, help="serving_stream: untimed requests")
     ap.add_argument("--rate", type=float, default=50.0, help="serving_stream: Poisson arrival rate, 1/s")
-    ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="default fp64 (serving_stream: mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=200000, help="abP elements in the oracle sample")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg of an FP64 run")
+    ap.add_argument("--cpu-pair-points", type=float, default=3e11,
+                    help="largest (ab|P on C) block, in pair-points, the oracle sample may pick")
     ap.add_argument("--tiling", default="0,0,0,0", help="wm,wn,stage_chunks,ksplit (0 = library default)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "contract_traffic.json"))
     ap.add_argument("--no-ri", action="store_true", help="skip the RI-assembly measurement after the steps")
@@ -71,19 +77,88 @@ def tiling_is_default(args, tuning):
     return tuning is None and all(int(x) == 0 for x in args.tiling.split(","))
 
 
-def sample_elements(job, n_abp, rng):
-    """Seeded sample of output elements of every kind (S, T, V, PQ, abP)."""
-    nb, na = job.n_bf, job.n_aux
+def third_atom_blocks(job):
+    """The (ab|P on C) blocks of the job, one per grid G(A,B|C): (A, B, C, points, pair-points).
+    These are the job's dominant work; the point count follows the grid spec (refined at C)."""
+    bat = job.basis[:, 0].astype(int)
+    xat = job.aux[:, 0].astype(int)
+    out = []
+    for A in range(job.n_atoms):
+        for B in range(A + 1, job.n_atoms):
+            sp = job.spec_for(A, B)
+            pts = (sp.n_mu * sp.n_nu * sp.n_phi + 8 * (sp.n_sp ** 3 - 1)) * sp.q ** 3
+            for C in range(job.n_atoms):
+                if C in (A, B):
+                    continue
+                el = int(np.sum(bat == A)) * int(np.sum(bat == B)) * int(np.sum(xat == C))
+                if el:
+                    out.append((A, B, C, pts, float(el) * pts))
+    return out
+
+
+def oracle_sample(job, rng, max_pp, n_aux_per_block=None):
+    """Seeded oracle sample: every (ab|P on C) element of one grid G(A,B|C) chosen at random among the
+    blocks of at most max_pp pair-points (the smallest block if none is), or only n_aux_per_block of
+    its P; plus 4 S, T, V and (P|Q) elements of the same atom pair (its other grids).
+    Returns (kinds, I, J, K, description)."""
+    blocks = third_atom_blocks(job)
+    fit = [b for b in blocks if b[4] <= max_pp] or [min(blocks, key=lambda b: b[4])]
+    A, B, C, pts, _ = fit[int(rng.integers(len(fit)))]
+    bat = job.basis[:, 0].astype(int)
+    xat = job.aux[:, 0].astype(int)
+    fa, fb, pc = np.flatnonzero(bat == A), np.flatnonzero(bat == B), np.flatnonzero(xat == C)
+    if n_aux_per_block:
+        pc = np.sort(rng.choice(pc, size=min(n_aux_per_block, pc.size), replace=False))
     kinds, I, J, K = [], [], [], []
-    for kind, n in ((0, 6), (1, 6), (2, 6), (3, 6)):
-        lim = na if kind == 3 else nb
-        for _ in range(n):
-            a, b = sorted(rng.integers(0, lim, size=2))
-            kinds.append(kind); I.append(a); J.append(b); K.append(0)
-    for _ in range(n_abp):
-        a, b = sorted(rng.integers(0, nb, size=2))
-        kinds.append(4); I.append(a); J.append(b); K.append(int(rng.integers(0, na)))
-    return np.array(kinds), np.array(I), np.array(J), np.array(K)
+    for P in pc:
+        for a in fa:
+            for b in fb:
+                kinds.append(4); I.append(int(a)); J.append(int(b)); K.append(int(P))
+    pa, pb = np.flatnonzero(xat == A), np.flatnonzero(xat == B)
+    for kd in range(4):
+        for _ in range(4):
+            if kd == 3:
+                if not (pa.size and pb.size):
+                    continue
+                kinds.append(3); I.append(int(rng.choice(pa))); J.append(int(rng.choice(pb)))
+            else:
+                kinds.append(kd); I.append(int(rng.choice(fa))); J.append(int(rng.choice(fb)))
+            K.append(0)
+    desc = (f"(ab|P on C) block of G({A},{B}|{C}) ({pts} points): {fa.size}x{fb.size}x{pc.size} elements, "
+            f"plus S/T/V/(P|Q) elements of atoms {A},{B}")
+    return np.array(kinds), np.array(I), np.array(J), np.array(K), desc
+
+
+def cpu_baseline_leg(job, outs, args, pair_points_job):
+    """The FP64 oracle on a seeded grid-confined sample of the job (all host cores; then one core on a
+    smaller sample), scaled to pair-points/s; max-abs error of the GPU outputs on the sample."""
+    import oracle as O
+    kinds, I, J, K, desc = oracle_sample(job, np.random.default_rng(15204), args.cpu_pair_points)
+    cores = O.set_threads(0)
+    c0 = time.perf_counter()
+    vals, wpp = O.compute_elements(job, kinds, I, J, K)
+    cdt = time.perf_counter() - c0
+    host = {k: v.cpu().numpy() for k, v in outs.items()}
+    got = np.array([host["abP"][p, a, b] if kd == 4 else host[("S", "T", "V", "PQ")[kd]][a, b]
+                    for kd, a, b, p in zip(kinds, I, J, K)])
+    err = {name: float(np.max(np.abs(got[kinds == kd] - vals[kinds == kd]))) if np.any(kinds == kd) else None
+           for kd, name in enumerate(("S", "T", "V", "PQ", "abP"))}
+    rate = wpp / cdt
+    # one core: the smallest block, a few of its auxiliary functions
+    k1, i1, j1, p1, desc1 = oracle_sample(job, np.random.default_rng(15205), 0.0, n_aux_per_block=30)
+    O.set_threads(1)
+    c1 = time.perf_counter()
+    _, wpp1 = O.compute_elements(job, k1, i1, j1, p1)
+    cdt1 = time.perf_counter() - c1
+    O.set_threads(cores)
+    base = {"value": rate, "unit": "pair·points/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"{len(kinds)} seeded elements: {desc}; {wpp:.3e} pair-points in {cdt:.1f} s; the whole "
+                       f"job ({pair_points_job:.3e} pair-points) would take {pair_points_job / rate:.0f} s at "
+                       f"this rate"),
+            "single_thread": {"value": wpp1 / cdt1, "unit": "pair·points/s", "cores": 1,
+                              "sample": f"{len(k1)} seeded elements: {desc1}; {wpp1:.3e} pair-points in "
+                                        f"{cdt1:.1f} s"}}
+    return base, err
 
 
 def main():
@@ -112,7 +187,7 @@ def main():
     if args.workload in ("grid_ladder", "nsp_sweep", "geometry_scan"):
         return accuracy_bench(args, psint, W)
     job = W.WORKLOADS[args.workload]()
-    prec = args.precision or job.precision
+    prec = args.precision or "fp64"
     ctx = psint.Context(0)
     wm, wn, sc, ks = (int(x) for x in args.tiling.split(","))
     if wm or wn or sc or ks:
@@ -124,34 +199,15 @@ def main():
                   "device_ms": {f"{t['wm']}x{t['wn']}x{t['stage_chunks']}": round(t["device_ms"], 3)
                                 for t in table}}
         print(f"[bench] autotune: {tuning}", flush=True)
-    # device outputs allocated once; the job's inputs are a few KB of host structs
-    dev = torch.device("cuda:0")
     nb, na = job.n_bf, job.n_aux
-    outs = {"S": torch.empty((nb, nb), dtype=torch.float64, device=dev),
-            "T": torch.empty((nb, nb), dtype=torch.float64, device=dev),
-            "V": torch.empty((nb, nb), dtype=torch.float64, device=dev),
-            "PQ": torch.empty((na, na), dtype=torch.float64, device=dev),
-            "PQ_chol": torch.empty((na, na), dtype=torch.float64, device=dev),
-            "abP": torch.empty((na, nb, nb), dtype=torch.float64, device=dev)}
+    outs = device_outputs(torch, nb, na)
     print(f"[bench] workload={job.name} precision={prec} n_bf={nb} n_aux={na}", flush=True)
-    for i in range(args.warmup):
-        ctx.compute(job, precision=prec, device=True, out_tensors=outs)
-        print(f"[bench] warmup {i + 1}/{args.warmup} done", flush=True)
-    torch.cuda.synchronize()
-    lat, contract_ms, stats = [], [], None
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        s0 = time.perf_counter()
-        _, stats, rc = ctx.compute(job, precision=prec, device=True, out_tensors=outs)
-        lat.append((time.perf_counter() - s0) * 1e3)
-        contract_ms.append(stats["contract_ms"])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    print(f"[bench] {args.steps} steps in {elapsed:.3f}s", flush=True)
+    run = timed_steps(ctx, job, prec, outs, args.steps, args.warmup, torch)
+    lat, stats, rc, elapsed = run["lat"], run["stats"], run["rc"], run["elapsed"]
     pp = stats["pair_points"]
     value = pp * args.steps / elapsed
     flops = stats["contract_flops"]
-    mean_contract_s = float(np.mean(contract_ms)) / 1e3
+    mean_contract_s = float(np.mean(run["contract_ms"])) / 1e3
     achieved = flops / mean_contract_s
     traffic = None
     if os.path.exists(args.traffic_json):
@@ -182,44 +238,89 @@ def main():
                       "pair_points_per_step": pp, "precision": prec, "passes": int(stats["n_passes"]),
                       "graph_replay": bool(stats["graph_replay"]),
                       "tiling": tuning["chosen"] if tuning else args.tiling},
-           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+           "latency_ms": latency_summary(lat),
            "roofline": roofline}
     if tuning:
         out["autotune"] = tuning
-    if prec == "mixed":
+    PQ = outs["PQ"].cpu().numpy()
+    out["metric_min_eigenvalue"] = {"PQ": float(np.linalg.eigvalsh(PQ)[0]), "PQ_max": float(np.max(np.diag(PQ))),
+                                    "cholesky_status": int(rc)}
+    if prec == "fp64" and not args.no_mixed:
+        out["mixed"] = mixed_leg(ctx, job, outs, torch, max(2, args.steps // 4))
+    elif prec == "mixed":
         # every element of the mixed result against one FP64 run of the same job on the device (the
         # FP64 path equals the oracle to ~1e-12, checked by the sampled oracle comparison and tests)
         ref, _, _ = ctx.compute(job, precision="fp64")
-        err = {}
-        for k in ("S", "T", "V", "PQ", "abP"):
-            got = outs[k].cpu().numpy()
-            d = float(np.max(np.abs(got - ref[k]))) if ref[k].size else 0.0
-            scale = float(np.max(np.abs(ref[k]))) if ref[k].size else 0.0
-            err[k] = {"max_abs": d, "max_abs_over_max_element": d / scale if scale else 0.0}
-        out["error_vs_fp64_full"] = err
+        out["error_vs_fp64_full"] = full_error({k: v.cpu().numpy() for k, v in outs.items()}, ref)
     if not args.no_ri:
         out["ri_assembly"] = ri_leg(ctx, outs, rc, psint)
     if not args.no_cpu_baseline:
-        import oracle as O
-        rng = np.random.default_rng(15204)
-        kinds, I, J, K = sample_elements(job, args.cpu_sample, rng)
-        cores = O.set_threads(0)
-        c0 = time.perf_counter()
-        vals, wpp = O.compute_elements(job, kinds, I, J, K)
-        cdt = time.perf_counter() - c0
-        host = {k: v.cpu().numpy() for k, v in outs.items()}
-        got = np.empty(len(kinds))
-        for e, (kd, a, b, p) in enumerate(zip(kinds, I, J, K)):
-            got[e] = host["abP"][p, a, b] if kd == 4 else host[("S", "T", "V", "PQ")[kd]][a, b]
-        err = {name: float(np.max(np.abs(got[kinds == kd] - vals[kinds == kd])))
-               for kd, name in enumerate(("S", "T", "V", "PQ", "abP"))}
-        out["cpu_baseline"] = {"value": wpp / cdt, "unit": "pair·points/s", "cores": int(cores),
-                               "kind": "oracle",
-                               "sample": f"{len(kinds)} seeded elements (6 each of S/T/V/PQ, "
-                                         f"{args.cpu_sample} of (ab|P)) of the same job, "
-                                         f"{wpp:.3e} pair-points in {cdt:.1f} s"}
-        out["error_vs_fp64_oracle"] = err
+        print("[bench] oracle sample on the host cores", flush=True)
+        out["cpu_baseline"], out["error_vs_fp64_oracle"] = cpu_baseline_leg(job, outs, args, pp)
     print(json.dumps(out), flush=True)
+
+
+def device_outputs(torch, nb, na):
+    """Device output tensors, allocated once; the job's inputs are a few KB of host structs."""
+    dev = torch.device("cuda:0")
+    return {"S": torch.empty((nb, nb), dtype=torch.float64, device=dev),
+            "T": torch.empty((nb, nb), dtype=torch.float64, device=dev),
+            "V": torch.empty((nb, nb), dtype=torch.float64, device=dev),
+            "PQ": torch.empty((na, na), dtype=torch.float64, device=dev),
+            "PQ_chol": torch.empty((na, na), dtype=torch.float64, device=dev),
+            "abP": torch.empty((na, nb, nb), dtype=torch.float64, device=dev)}
+
+
+def timed_steps(ctx, job, prec, outs, steps, warmup, torch):
+    """warmup untimed jobs, then `steps` timed ones bracketed by device synchronisation."""
+    for i in range(warmup):
+        ctx.compute(job, precision=prec, device=True, out_tensors=outs)
+        print(f"[bench] {prec} warmup {i + 1}/{warmup} done", flush=True)
+    torch.cuda.synchronize()
+    lat, contract_ms, stats, rc = [], [], None, None
+    t0 = time.perf_counter()
+    for i in range(steps):
+        s0 = time.perf_counter()
+        _, stats, rc = ctx.compute(job, precision=prec, device=True, out_tensors=outs)
+        lat.append((time.perf_counter() - s0) * 1e3)
+        contract_ms.append(stats["contract_ms"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"[bench] {prec}: {steps} steps in {elapsed:.3f}s", flush=True)
+    return {"lat": lat, "contract_ms": contract_ms, "stats": stats, "rc": rc, "elapsed": elapsed}
+
+
+def latency_summary(lat):
+    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+            "max": float(np.max(lat)), "steps": [round(float(x), 3) for x in lat]}
+
+
+def full_error(got, ref):
+    """Max-abs error of every element per output type, and over that type's largest element."""
+    err = {}
+    for k in ("S", "T", "V", "PQ", "abP"):
+        d = float(np.max(np.abs(got[k] - ref[k]))) if ref[k].size else 0.0
+        scale = float(np.max(np.abs(ref[k]))) if ref[k].size else 0.0
+        err[k] = {"max_abs": d, "max_abs_over_max_element": d / scale if scale else 0.0}
+    return err
+
+
+def mixed_leg(ctx, job, outs64, torch, steps):
+    """The same job in mixed precision after the FP64 steps: throughput, contraction rate against the
+    FP32 peak, and every output element against the FP64 run."""
+    outs = device_outputs(torch, job.n_bf, job.n_aux)
+    run = timed_steps(ctx, job, "mixed", outs, steps, 1, torch)
+    st = run["stats"]
+    achieved = st["contract_flops"] / (float(np.mean(run["contract_ms"])) / 1e3)
+    res = {"value": st["pair_points"] * steps / run["elapsed"], "unit": "pair·points/s", "steps": steps,
+           "ms_per_step": run["elapsed"] * 1e3 / steps, "passes": int(st["n_passes"]),
+           "latency_ms": latency_summary(run["lat"]),
+           "contract_tflops": achieved / 1e12, "contract_frac_fp32_peak": achieved / PEAK["mixed"],
+           "error_vs_fp64_full": full_error({k: v.cpu().numpy() for k, v in outs.items()},
+                                            {k: v.cpu().numpy() for k, v in outs64.items()})}
+    del outs
+    torch.cuda.empty_cache()
+    return res
 
 
 def ri_leg(ctx, outs, rc, psint, reps=3):
