@@ -29,6 +29,10 @@ hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_mfma_rate(bool fp64, int blocks, int iters, double* out, hipStream_t st);
 hipError_t launch_symmetrize(double* X, int n, hipStream_t st);
 hipError_t launch_cholesky(const double* A, double* L, int n, int* status, hipStream_t st);
+
+// Offset, within the 64-byte status slot of the staged tables, at which the host receives the
+// device's status word after a job (the slot's first half is staged to the device, zeroed).
+constexpr size_t kStatusReadback = 32;
 hipError_t launch_grid_points(const GridDev& G, const double* lines, const double* RA, double* xyzw, hipStream_t st);
 hipError_t launch_eval_points(int what, const ShellDev& sh, const MEntry& me, const double* c, const double* X,
                               const double* Y, const double* Z, int64_t n, double* out, hipStream_t st);
@@ -359,7 +363,10 @@ int32_t enqueue_outputs(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, co
     HIP_TRY(hipMemcpyAsync(dst, out + o.off, o.bytes, kind, s.stream));
     bo += o.bytes;
   }
-  HIP_TRY(hipMemcpyAsync((char*)s.pinned + L.status, base + L.status, sizeof(int), hipMemcpyDeviceToHost, s.stream));
+  // The status word is read back into the second half of its 64-byte staging slot: the first half is
+  // part of the tables the next run of the same job copies to the device, and must stay zero.
+  HIP_TRY(hipMemcpyAsync((char*)s.pinned + L.status + kStatusReadback, base + L.status, sizeof(int),
+                         hipMemcpyDeviceToHost, s.stream));
   HIP_TRY(hipEventRecord(s.ev_end, s.stream));
   return PS_OK;
 }
@@ -450,7 +457,7 @@ int32_t prepare_slot(ps_ctx* ctx, Slot& s, const ps_job* job, Plan& plan, Layout
 
 int32_t finish_stats(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, ps_job_stats* st, double total_ms,
                      double queue_ms) {
-  int status = *(int*)((char*)s.pinned + L.status);
+  int status = *(int*)((char*)s.pinned + L.status + kStatusReadback);
   if (st) {
     std::memset(st, 0, sizeof *st);
     st->n_grids = (int64_t)p.grids.size();

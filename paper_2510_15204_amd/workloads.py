@@ -13,14 +13,14 @@ Recipe (the paper prints no worked inputs, so every workload is synthetic):
   * Shells of a channel are sorted by descending zeta; basis principal quantum numbers are
     n = l + 1 + (k mod (n_max - l)); auxiliary functions use n = l + 1.
   * Every m = -l..l of a shell is enumerated (Section 3: all m degrees of freedom).
-  * Auxiliary exponent ranges run from twice the atom's smallest basis exponent (Section 3: aux
-    exponents come from sums of pairs of basis exponents) to four times its largest, unless the
-    workload states them.  With the quadruple-zeta-sized auxiliary shells spread over l = 0..4 as
-    (10, 8, 7, 6, 6) per heavy atom and (7, 5, 4, 3, 3) per H, this keeps adjacent exponents of a
-    channel about 1.5x apart: the Coulomb metric of the triatomic QZ job then has its smallest
-    eigenvalue at 1.2e-6 (of 373) on its 96x96x48-point grids, against -1.9e-6 with 16 s shells over
-    twice the basis range (exactly, 2.5e-12: so close to singular that the quadrature error of
-    those grids made it indefinite).
+  * Auxiliary exponent ranges run from twice the atom's smallest basis exponent to twice its largest
+    (Section 3: aux exponents come from sums of pairs of basis exponents), unless the workload states
+    them.  The quadruple-zeta-sized sets reach four times the largest instead and spread their shells
+    over l = 0..4 as (10, 8, 7, 6, 6) per heavy atom and (7, 5, 4, 3, 3) per H, which keeps adjacent
+    exponents of a channel about 1.5x apart: the Coulomb metric of the triatomic QZ job then has its
+    smallest eigenvalue at 1.2e-6 (of 373) on its 96x96x48-point grids, against -1.9e-6 with 16 s
+    shells over twice the basis range (exactly, 2.5e-12: so close to singular that the quadrature
+    error of those grids made it indefinite).
   * Grid sizes: the workloads are quoted in quadrature points per axis; with Q = 4 Gauss-Legendre
     points per cell and axis the cell counts are points / 4.
   * Seeds: numpy PCG64 from SeedSequence(15204).spawn(5)[i] for workload i (0-based).
@@ -160,7 +160,7 @@ def build_basis(rng, Z: Sequence[int], family: str, aux_family: str, n_max: Opti
             alo, ahi = aux_ranges[int(z)]
         else:
             lo, hi = (basis_ranges or ZETA_RANGE)[int(z)]
-            alo, ahi = 2 * lo, 4 * hi
+            alo, ahi = 2 * lo, (4 if aux_family == "auxQZ" else 2) * hi
         aux += make_shells(rng, a, SHELLS[_kind(z)][aux_family], alo, ahi, None, aux=True)
     return _as_array(basis), _as_array(aux)
 

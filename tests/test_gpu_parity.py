@@ -174,6 +174,36 @@ def test_not_positive_definite_metric_reported(ctx):
     _compare(got, ref, TOL64, "not PD")
 
 
+def test_repeated_not_positive_definite_job_factors_every_time():
+    """A job whose metric is not positive definite only in its second 32-column panel (35 auxiliary
+    functions, the last a copy of the first), run three times on one context (the repeats reuse its
+    plan and replay captured graphs): each run reports NOT_PD after factoring the first panel, so
+    that panel equals the oracle's factor of the leading 32 x 32 block every time (a status left
+    set by an earlier run would skip the factorisation and leave (P|Q) itself there)."""
+    xyz = np.array([[0.0, 0.0, 0.7], [0.0, 0.0, -0.7]])
+    aux = []
+    for a in range(2):
+        aux += [[a, 1, 0, 0, z] for z in (1.0, 3.0)]
+        aux += [[a, 2, 1, m, 1.5] for m in (-1, 0, 1)]
+        aux += [[a, 3, 2, m, 2.0] for m in range(-2, 3)]
+        aux += [[a, 4, 3, m, 2.2] for m in range(-3, 4)]
+    aux.append(list(aux[0]))
+    assert len(aux) == 35
+    job = MiniJob(xyz, [1, 1], [[0, 1, 0, 0, 1.0], [1, 1, 0, 0, 1.0]], aux, Spec(10, 10, 6))
+    c = psint.Context(0)
+    try:
+        runs = [c.compute(job) for _ in range(3)]
+    finally:
+        c.close()
+    PQ = runs[0][0]["PQ"]
+    L32 = np.linalg.cholesky(PQ[:32, :32])
+    for got, st, rc in runs:
+        assert rc == psint.PS_E_NOT_PD
+        assert np.max(np.abs(got["PQ_chol"][:32, :32] - L32)) < 1e-12 * np.max(np.abs(L32))
+        assert np.array_equal(got["PQ_chol"], runs[0][0]["PQ_chol"])
+    assert runs[2][1]["graph_replay"] == 1
+
+
 @pytest.mark.parametrize("bad", ["l_ge_n", "neg_zeta", "atom_index", "coincident", "spec", "too_high_l"])
 def test_invalid_inputs_rejected(ctx, bad):
     xyz = np.array([[0.0, 0.0, 0.7], [0.0, 0.0, -0.7]])
