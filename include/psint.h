@@ -210,6 +210,22 @@ int32_t ps_autotune(ps_ctx* ctx, const ps_job* job, int32_t reps, ps_tuning* bes
 int32_t ps_ri_assemble(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, int32_t location, const double* abP,
                        const double* L, double* B, double* eri, double* device_ms);
 
+/* ---- allocation-free RI assembly ----------------------------------------------------------- */
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The same computation and layouts as ps_ri_assemble with all four
+ * arrays on the context's device (abP, L inputs; B, eri outputs, NULL = not wanted), but the call's
+ * scratch -- the gathered (ab|P) rows and B (n_aux x n_pair each; no B scratch when B is given), the
+ * transformed factor (n_aux x n_aux) and the product's tile list -- lives in a static device array of
+ * PS_RI_NOALLOC_SCRATCH_BYTES per GPU, held by every GPU the library runs on until the process ends.
+ * Nothing is allocated: no hipMalloc, hipFree or context memory.  Sizes whose scratch exceeds the
+ * array return PS_E_NOMEM with the need in ps_last_error.  The kernels are enqueued on the context's
+ * synchronous stream and the call returns without waiting: the outputs are ready when that stream
+ * reaches this point.  Every call on one GPU shares that GPU's array: calls on one context run in
+ * order on its stream, but calls that can overlap on one GPU (other contexts or streams) race. */
+#define PS_RI_NOALLOC_SCRATCH_BYTES (64u << 20)
+int32_t ps_ri_assemble_noalloc(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, const double* abP, const double* L,
+                               double* B, double* eri);
+
 const char* ps_status_string(int32_t status);
 /* Last error text of the context (valid until the next call on it); ctx may be NULL. */
 const char* ps_last_error(ps_ctx* ctx);

@@ -556,6 +556,8 @@ int32_t ps_create(int32_t hip_device, size_t hbm_budget_bytes, void* stream, ps_
     delete ctx;
     return rc;
   }
+  // set-up of the allocation-free RI entry point on this device (it retries on its first call)
+  (void)ri_noalloc_init(hip_device);
   *out = ctx;
   return PS_OK;
 }

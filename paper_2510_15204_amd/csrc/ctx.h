@@ -96,5 +96,7 @@ void serve_shutdown(ps_ctx* ctx);
 void* pool_alloc(ps_ctx* ctx, size_t bytes, size_t* got);
 void pool_release(ps_ctx* ctx, void* p, size_t bytes);
 void pool_destroy(ps_ctx* ctx);
+// Looks up the allocation-free RI entry point's static scratch address on `device` (current).
+int32_t ri_noalloc_init(int device);
 
 }  // namespace psint

@@ -8,6 +8,9 @@
 //   ri_syrk_kernel    128 x 128 output tiles on or above the diagonal, v_mfma_f64_16x16x4f64 with
 //                     the 16-row slices of B staged in LDS; the mirror tile is written through an LDS
 //                     transpose so both halves are stored with coalesced rows
+//   ri_tiles_kernel   the product's tile list, written on the device (allocation-free entry point)
+// Host entry points: ps_ri_assemble (scratch from the context's device memory) and
+// ps_ri_assemble_noalloc (scratch in a fixed static device array; device arrays only).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,6 +22,7 @@
 
 #include "ctx.h"
 #include "jobs.h"
+#include "ri_tiles.h"
 
 namespace psint {
 
@@ -321,6 +325,57 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
     }
 }
 
+// Tile list of ri_syrk_kernel, one entry per thread, in the order of ri_syrk_tile.
+__global__ __launch_bounds__(256) void ri_tiles_kernel(int64_t nt, int64_t ntiles, int2* __restrict__ tiles) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  int i, j;
+  ri_syrk_tile(t, nt, &i, &j);
+  tiles[t] = make_int2(i, j);
+}
+
+// The kernel chain of one RI assembly on `st`: gather, inverses of the diagonal blocks, the
+// transformed factor, the forward substitution into Bo and, when C is given, the product over the
+// ntiles tiles listed at `tiles`.  X, G and Bo are the call's scratch (Bo may be the caller's B).
+hipError_t ri_launch_chain(hipStream_t st, int n_bf, int n_aux, const double* abP, const double* L, double* X,
+                           double* G, double* Bo, const int2* tiles, int64_t ntiles, double* C) {
+  const int64_t na = n_aux, npair = (int64_t)n_bf * (n_bf + 1) / 2;
+  hipLaunchKernelGGL(ri_gather_kernel, dim3((unsigned)((n_bf + 3) / 4), (unsigned)n_aux), dim3(256), 0, st, abP,
+                     n_bf, X);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nblk = (n_aux + TR_ROWS - 1) / TR_ROWS;
+  hipLaunchKernelGGL(ri_inv_kernel, dim3((unsigned)nblk), dim3(64), 0, st, L, n_aux, G);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  int64_t blocks = (na * na + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(ri_offdiag_kernel, dim3((unsigned)blocks), dim3(256), 0, st, L, n_aux, G);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (n_aux <= SB_MAX_NA) {
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void*)ri_subst_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, SB_MAX_LDS);
+    if (attr != hipSuccess) return attr;
+    const size_t lds = (size_t)((n_aux + TR_ROWS - 1) / TR_ROWS * TR_ROWS) * SB_LD * sizeof(double);
+    hipLaunchKernelGGL(ri_subst_kernel, dim3((unsigned)((npair + SB_W - 1) / SB_W)), dim3(256), lds, st,
+                       (const double*)G, n_aux, npair, (const double*)X, Bo);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else {
+    for (int r0 = 0; r0 < n_aux; r0 += TR_ROWS) {
+      const int below = n_aux - std::min(n_aux, r0 + TR_ROWS);
+      hipLaunchKernelGGL(ri_solve_kernel,
+                         dim3((unsigned)((npair + UP_T - 1) / UP_T), (unsigned)(1 + (below + UP_T - 1) / UP_T)),
+                         dim3(256), 0, st, (const double*)G, n_aux, npair, X, Bo, r0);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  if (C) {
+    hipLaunchKernelGGL(ri_syrk_kernel, dim3((unsigned)ntiles), dim3(256), 0, st, (const double*)Bo, n_aux, npair,
+                       tiles, C);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 }  // namespace psint
 
 using namespace psint;
@@ -340,6 +395,15 @@ struct RiScratch {
     if (!p) return;
     (void)hipStreamSynchronize(st);
     pool_release(ctx, p, size);
+  }
+};
+
+// Timing events of one call, destroyed on every return path.
+struct RiEvents {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~RiEvents() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
   }
 };
 
@@ -427,70 +491,113 @@ extern "C" int32_t ps_ri_assemble(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, int3
   }
   std::vector<int2> tl;
   if (eri) {
-    // upper-triangle tiles row by row, cut into 8 contiguous runs, one per XCD (work-groups go to
-    // XCD blockIdx mod 8): the tiles of one run share their row block X[:, i0 .. i0 + 127] in that
-    // XCD's L2
-    const int nt = (int)((npair + SY_T - 1) / SY_T);
-    std::vector<int2> rows;
-    rows.reserve(ntiles);
-    for (int i = 0; i < nt; ++i)
-      for (int j = i; j < nt; ++j) rows.push_back(make_int2(i, j));
-    constexpr size_t NX = 8;
-    size_t beg[NX + 1];
-    for (size_t x = 0; x <= NX; ++x) beg[x] = rows.size() * x / NX;
-    tl.reserve(rows.size());
-    for (size_t r = 0; tl.size() < rows.size(); ++r)
-      for (size_t x = 0; x < NX; ++x)
-        if (beg[x] + r < beg[x + 1]) tl.push_back(rows[beg[x] + r]);
+    tl.resize(ntiles);
+    const int64_t nt = (npair + SY_T - 1) / SY_T;
+    for (size_t t = 0; t < ntiles; ++t) ri_syrk_tile((int64_t)t, nt, &tl[t].x, &tl[t].y);
     RI_TRY(hipMemcpyAsync(d_tiles, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, st));
   }
-  hipEvent_t e0, e1;
-  RI_TRY(hipEventCreate(&e0));
-  RI_TRY(hipEventCreate(&e1));
-  RI_TRY(hipEventRecord(e0, st));
-  hipLaunchKernelGGL(ri_gather_kernel, dim3((unsigned)((n_bf + 3) / 4), (unsigned)n_aux), dim3(256), 0, st, d_abp,
-                     n_bf, d_x);
-  RI_TRY(hipGetLastError());
-  // blocked forward substitution on the transformed factor, B into its own buffer
-  {
-    const int nblk = (n_aux + TR_ROWS - 1) / TR_ROWS;
-    hipLaunchKernelGGL(ri_inv_kernel, dim3((unsigned)nblk), dim3(64), 0, st, d_l, n_aux, d_g);
-    RI_TRY(hipGetLastError());
-    int64_t blocks = (na * na + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(ri_offdiag_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d_l, n_aux, d_g);
-    RI_TRY(hipGetLastError());
-    if (n_aux <= SB_MAX_NA) {
-      static const hipError_t attr =
-          hipFuncSetAttribute((const void*)ri_subst_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, SB_MAX_LDS);
-      RI_TRY(attr);
-      const size_t lds = (size_t)((n_aux + TR_ROWS - 1) / TR_ROWS * TR_ROWS) * SB_LD * sizeof(double);
-      hipLaunchKernelGGL(ri_subst_kernel, dim3((unsigned)((npair + SB_W - 1) / SB_W)), dim3(256), lds, st,
-                         (const double*)d_g, n_aux, npair, (const double*)d_x, d_b);
-      RI_TRY(hipGetLastError());
-    } else {
-      for (int r0 = 0; r0 < n_aux; r0 += TR_ROWS) {
-        const int below = n_aux - std::min(n_aux, r0 + TR_ROWS);
-        hipLaunchKernelGGL(ri_solve_kernel,
-                           dim3((unsigned)((npair + UP_T - 1) / UP_T), (unsigned)(1 + (below + UP_T - 1) / UP_T)),
-                           dim3(256), 0, st, (const double*)d_g, n_aux, npair, d_x, d_b, r0);
-        RI_TRY(hipGetLastError());
-      }
-    }
-  }
-  if (eri) {
-    hipLaunchKernelGGL(ri_syrk_kernel, dim3((unsigned)tl.size()), dim3(256), 0, st, (const double*)d_b, n_aux, npair,
-                       (const int2*)d_tiles, d_eri);
-    RI_TRY(hipGetLastError());
-  }
-  RI_TRY(hipEventRecord(e1, st));
+  RiEvents ev;
+  RI_TRY(hipEventCreate(&ev.e0));
+  RI_TRY(hipEventCreate(&ev.e1));
+  RI_TRY(hipEventRecord(ev.e0, st));
+  RI_TRY(ri_launch_chain(st, n_bf, n_aux, d_abp, d_l, d_x, d_g, d_b, d_tiles, (int64_t)tl.size(), d_eri));
+  RI_TRY(hipEventRecord(ev.e1, st));
   if (B) RI_TRY(hipMemcpyAsync(B, d_b, x_b, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
   if (eri && !dev) RI_TRY(hipMemcpyAsync(eri, d_eri, eri_b, hipMemcpyDeviceToHost, st));
   RI_TRY(hipStreamSynchronize(st));
   float ms = 0.0f;
-  RI_TRY(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  RI_TRY(hipEventElapsedTime(&ms, ev.e0, ev.e1));
   if (device_ms) *device_ms = ms;
+  return PS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Allocation-free RI assembly: the call's scratch lives in a fixed static device array, one copy per
+// GPU, held until the process ends.  Host code never passes the array's name to a kernel or copy (in
+// host code it is only a stand-in for the symbol): the device address of each GPU's copy is looked
+// up once per device with hipGetSymbolAddress and kept in scratch_ptr.
+// ---------------------------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[PS_RI_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+// Device address of `device`'s scratch copy; that device must be current.  Looked up on the first
+// call per device and kept.
+hipError_t scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (!scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[device] = p;
+  }
+  *out = scratch_ptr[device];
+  return hipSuccess;
+}
+
+}  // namespace
+
+namespace psint {
+
+// Called by ps_create with the context's device current, so that the allocation-free entry point
+// finds its scratch address already looked up.
+int32_t ri_noalloc_init(int device) {
+  void* p = nullptr;
+  return scratch_address(device, &p) == hipSuccess ? PS_OK : PS_E_DEVICE;
+}
+
+}  // namespace psint
+
+extern "C" int32_t ps_ri_assemble_noalloc(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, const double* abP,
+                                          const double* L, double* B, double* eri) {
+  if (!ctx) return PS_E_INVALID;
+  if (n_bf < 1 || n_aux < 1 || !abP || !L) {
+    ctx->err = "ri (no-alloc): n_bf, n_aux >= 1, abP and L required";
+    return PS_E_INVALID;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
+  std::lock_guard<std::mutex> sync_guard(ctx->sync_mu);
+  const int64_t nb = n_bf, na = n_aux, npair = nb * (nb + 1) / 2;
+  const int64_t nt = (npair + SY_T - 1) / SY_T;
+  const int64_t ntiles = eri ? nt * (nt + 1) / 2 : 0;
+  const size_t x_b = (size_t)na * npair * 8, g_b = (size_t)na * na * 8;
+  // X, then B unless the caller's B receives it, then G, then the tile list
+  const size_t off_x = 0;
+  size_t total = align256(x_b);
+  const size_t off_b = total;
+  if (!B) total = align256(total + x_b);
+  const size_t off_g = total;
+  total = align256(total + g_b);
+  const size_t off_t = total;
+  total = align256(total + (size_t)ntiles * sizeof(int2));
+  if (total > (size_t)PS_RI_NOALLOC_SCRATCH_BYTES) {
+    char buf[200];
+    snprintf(buf, sizeof buf,
+             "ri (no-alloc): needs %.1f MiB of scratch (n_aux %d, n_pair %lld%s), the static scratch holds %.1f MiB",
+             total / 1048576.0, n_aux, (long long)npair, B ? "" : ", B not given", PS_RI_NOALLOC_SCRATCH_BYTES / 1048576.0);
+    ctx->err = buf;
+    return PS_E_NOMEM;
+  }
+  void* base_v = nullptr;
+  RI_TRY(scratch_address(ctx->device, &base_v));
+  char* base = (char*)base_v;
+  double* d_x = (double*)(base + off_x);
+  double* d_b = B ? B : (double*)(base + off_b);
+  double* d_g = (double*)(base + off_g);
+  int2* d_tiles = (int2*)(base + off_t);
+  hipStream_t st = ctx->sync_slot.stream;
+  if (eri) {
+    hipLaunchKernelGGL(ri_tiles_kernel, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st, nt, ntiles,
+                       d_tiles);
+    RI_TRY(hipGetLastError());
+  }
+  RI_TRY(ri_launch_chain(st, n_bf, n_aux, abP, L, d_x, d_g, d_b, d_tiles, ntiles, eri));
   return PS_OK;
 }

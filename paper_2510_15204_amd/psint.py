@@ -110,13 +110,14 @@ def lib():
                                   C.POINTER(C.c_int32)]
         L.ps_ri_assemble.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp, _dp]
         L.ps_mfma_rate.argtypes = [vp, C.c_int32, _dp]
+        L.ps_ri_assemble_noalloc.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, vp]
         L.ps_status_string.argtypes = [C.c_int32]
         L.ps_status_string.restype = C.c_char_p
         L.ps_last_error.argtypes = [vp]
         L.ps_last_error.restype = C.c_char_p
         for f in ("ps_create", "ps_destroy", "ps_compute", "ps_submit", "ps_wait", "ps_grid_points",
                   "ps_eval_function", "ps_plan_work", "ps_set_tiling", "ps_autotune", "ps_ri_assemble",
-                  "ps_mfma_rate"):
+                  "ps_mfma_rate", "ps_ri_assemble_noalloc"):
             getattr(L, f).restype = C.c_int32
         _LIB = L
     return _LIB
@@ -137,7 +138,7 @@ def plan_work_host(job, precision=None):
 def exported_symbols():
     return ["ps_create", "ps_destroy", "ps_compute", "ps_submit", "ps_wait", "ps_grid_points",
             "ps_eval_function", "ps_plan_work", "ps_set_tiling", "ps_autotune", "ps_ri_assemble",
-            "ps_mfma_rate", "ps_status_string", "ps_last_error"]
+            "ps_mfma_rate", "ps_ri_assemble_noalloc", "ps_status_string", "ps_last_error"]
 
 
 def _spec(s) -> GridSpec:
@@ -261,6 +262,17 @@ class Context:
         self._check(lib().ps_ri_assemble(self.h, nb, na, 1 if dev else 0, ptr(abP), ptr(L), ptr(B), ptr(eri),
                                          C.byref(ms)))
         return B, eri, ms.value
+
+    def ri_assemble_noalloc(self, abP, L, B=None, eri=None):
+        """ps_ri_assemble_noalloc on device tensors: abP [P][a][b] and the lower factor L in, the
+        caller's B (n_aux x n_pair) and eri (n_pair x n_pair) tensors out (None = not wanted).  The
+        kernels are only enqueued on the context's stream; synchronise before reading the outputs."""
+        import torch
+        for t in (abP, L, B, eri):
+            assert t is None or (t.dtype == torch.float64 and t.is_cuda and t.is_contiguous())
+        na, nb = int(abP.shape[0]), int(abP.shape[1])
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+        self._check(lib().ps_ri_assemble_noalloc(self.h, nb, na, ptr(abP), ptr(L), ptr(B), ptr(eri)))
 
     def mfma_rate(self, precision="fp64"):
         """Measured matrix-pipe throughput of the device in TFLOP/s (ps_mfma_rate): FP64 MFMA for
