@@ -203,8 +203,11 @@ static void stage_meta(const Plan& p, const Layout& L, char* base, char* host) {
   std::vector<SegDev> segs(p.segs.size());
   for (size_t i = 0; i < p.segs.size(); ++i) {
     segs[i] = p.segs[i].dev;
-    segs[i].arr0 = base + L.arrays + p.arrays[p.segs[i].arr0].offset;
-    segs[i].arr1 = p.segs[i].arr1 >= 0 ? base + L.arrays + p.arrays[p.segs[i].arr1].offset : nullptr;
+    auto at = [&](int a) -> void* { return a >= 0 ? base + L.arrays + p.arrays[a].offset : nullptr; };
+    segs[i].arr0 = at(p.segs[i].arr0);
+    segs[i].arr1 = at(p.segs[i].arr1);
+    segs[i].arr0d = at(p.segs[i].arr0d);
+    segs[i].arr1d = at(p.segs[i].arr1d);
   }
   put(L.segs, segs.data(), segs.size() * sizeof(SegDev));
   const int32_t* ints_dev = (const int32_t*)(base + L.ints);
@@ -274,7 +277,7 @@ int32_t enqueue_segment(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, in
       const int n = lc.tile1 - lc.tile0;
       if (n <= 0) continue;
       const TileShape& sh = lc.shape;
-      if (mixed)
+      if (mixed && !lc.f64)
         HIP_TRY(launch_contract_mixed(sh.wm, sh.wn, sh.sc, tasks, tiles + lc.tile0, n, ws, st));
       else
         HIP_TRY(launch_contract_f64(sh.wm, sh.wn, sh.sc, tasks, tiles + lc.tile0, n, ws, st));
@@ -397,17 +400,22 @@ TileShape effective_shape(const ps_ctx* ctx, int32_t precision) {
     static std::mutex mu;
     static std::map<std::tuple<int, int, int, int, int>, int> cache;
     const bool mixed = precision == PS_PREC_MIXED;
-    auto resident = [&](int wm, int wn, int sc) {
-      const auto key = std::make_tuple(ctx->device, (int)mixed, wm, wn, sc);
+    auto resident_of = [&](bool mx, int wm, int wn, int sc) {
+      const auto key = std::make_tuple(ctx->device, (int)mx, wm, wn, sc);
       auto it = cache.find(key);
-      if (it == cache.end()) it = cache.emplace(key, contract_resident_workgroups(mixed, wm, wn, sc)).first;
+      if (it == cache.end()) it = cache.emplace(key, contract_resident_workgroups(mx, wm, wn, sc)).first;
       return it->second;
     };
+    auto resident = [&](int wm, int wn, int sc) { return resident_of(mixed, wm, wn, sc); };
     std::lock_guard<std::mutex> g(mu);
     t.slots = resident(t.wm, t.wn, t.sc);
     t.slots2 = resident(2, 2, t.sc);
     for (int w = 1; w < t.wn && w <= 3; ++w) t.slots_n[w] = resident(t.wm, w, t.sc);
     t.slots2n = resident(2, 1, t.sc);
+    if (mixed) {  // the FP64 two-index launches of a mixed job
+      t.slots2_f64 = resident_of(false, 2, 2, t.sc);
+      t.slots2n_f64 = resident_of(false, 2, 1, t.sc);
+    }
   }
   return t;
 }

@@ -190,7 +190,7 @@ __device__ __forceinline__ void inc_gamma_pair(int k_lo, int k_up, double x, dou
 // Y_lm = f * C_l^m (m >= 0) or f * S_l^|m| (m < 0) with f from the host.
 // ------------------------------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void eval_kernel(const SegDev* __restrict__ segs, int nseg,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void eval_kernel(const SegDev* __restrict__ segs, int nseg,
                                                    const GridDev* __restrict__ grids,
                                                    const double* __restrict__ lines,
                                                    const ShellDev* __restrict__ shells,
@@ -213,22 +213,36 @@ __global__ __launch_bounds__(256) void eval_kernel(const SegDev* __restrict__ se
   const int64_t gw = (b - S.block0) * 256 + __builtin_amdgcn_readfirstlane(threadIdx.x & ~63);
   const int64_t g = gw + lane;
   typedef __attribute__((address_space(1))) T GT;
+  typedef __attribute__((address_space(1))) double GD;
   GT* __restrict__ w0 = (GT*)S.arr0 + gw * S.nf;
   GT* __restrict__ w1 = (GT*)S.arr1 + gw * S.nf;
   const uint32_t loff = (uint32_t)((lane >> 4) * S.nf * KC + (lane & 15));
-  auto put0 = [&](int col, T v) { w0[(int64_t)col * KC + loff] = v; };
-  auto put1 = [&](int col, T v) { w1[(int64_t)col * KC + loff] = v; };
+  // FP32 evaluation (mixed jobs): a column may go to the FP32 array, to its FP64 twin, or both
+  // (the pointers are uniform over the segment); FP64 evaluation: the FP64 array alone
+  constexpr bool F32 = sizeof(T) == 4;
+  GD* __restrict__ d0 = (GD*)S.arr0d + gw * S.nf;
+  GD* __restrict__ d1 = (GD*)S.arr1d + gw * S.nf;
+  const bool has0 = !F32 || S.arr0 != nullptr, has1 = !F32 || S.arr1 != nullptr;
+  const bool has0d = F32 && S.arr0d != nullptr, has1d = F32 && S.arr1d != nullptr;
+  auto put0 = [&](int col, double v) {
+    if (has0) w0[(int64_t)col * KC + loff] = (T)v;
+    if (has0d) d0[(int64_t)col * KC + loff] = v;
+  };
+  auto put1 = [&](int col, double v) {
+    if (has1) w1[(int64_t)col * KC + loff] = (T)v;
+    if (has1d) d1[(int64_t)col * KC + loff] = v;
+  };
   if (g >= G.npts) {  // padding points: every column exactly zero
     if (S.mode == EV_WEIGHTS) {
-      for (int it = 0; it < S.n_items; ++it) put0(wcols[S.item_off + it].col, (T)0);
+      for (int it = 0; it < S.n_items; ++it) put0(wcols[S.item_off + it].col, 0.0);
     } else {
       for (int s = S.item_off; s < S.item_off + S.n_items; ++s) {
         const ShellDev sh = shells[s];
         for (int e = 0; e < sh.nm; ++e) {
           const int col = ments[sh.m_off + e].col;
           if (col < 0) continue;
-          put0(col, (T)0);
-          if (S.mode == EV_CHI_KIN) put1(col, (T)0);
+          put0(col, 0.0);
+          if (S.mode == EV_CHI_KIN) put1(col, 0.0);
         }
       }
     }
@@ -247,7 +261,7 @@ __global__ __launch_bounds__(256) void eval_kernel(const SegDev* __restrict__ se
         if (W.zC != 0.0) pot += W.zC / geo.r[2];
         v = -geo.w * pot;
       }
-      put0(W.col, (T)v);
+      put0(W.col, v);
     }
     return;
   }
@@ -326,13 +340,13 @@ __global__ __launch_bounds__(256) void eval_kernel(const SegDev* __restrict__ se
         if (mm > l) break;
         if (ep[mm].col >= 0) {
           const double Yh = C[mm] * ep[mm].f;
-          put0(ep[mm].col, (T)(rad * Yh));
-          if (S.mode == EV_CHI_KIN) put1(ep[mm].col, (T)(kin * Yh));
+          put0(ep[mm].col, rad * Yh);
+          if (S.mode == EV_CHI_KIN) put1(ep[mm].col, kin * Yh);
         }
         if (mm > 0 && en[mm].col >= 0) {
           const double Yh = Sv[mm] * en[mm].f;
-          put0(en[mm].col, (T)(rad * Yh));
-          if (S.mode == EV_CHI_KIN) put1(en[mm].col, (T)(kin * Yh));
+          put0(en[mm].col, rad * Yh);
+          if (S.mode == EV_CHI_KIN) put1(en[mm].col, kin * Yh);
         }
       }
     }

@@ -390,7 +390,6 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
   p.n_bf = job->n_bf;
   p.n_aux = job->n_aux;
   p.precision = job->precision;
-  p.elem_size = job->precision == PS_PREC_MIXED ? 4 : 8;
   const int N = p.n_atoms, nb = p.n_bf, na = p.n_aux;
 
   // internal FP64 output buffer: [S | T | V | PQ | abP | L]
@@ -457,6 +456,7 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
     ArrayHost a;
     a.grid = grid;
     a.nf = nf;
+    a.es = p.precision == PS_PREC_MIXED ? 4 : 8;
     a.offset = 0;
     a.map = std::move(map);
     a.map_off = -1;
@@ -829,9 +829,49 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
     p.n_points += g.dev.npts;
   }
 
+  // ---- mixed precision: the two-index tasks (S, T, V, (P|Q)) keep FP64 operands ----
+  // An array read only by two-index tasks is held in FP64; one read by (ab|P) tasks as well gets an
+  // FP64 twin beside its FP32 copy.  The FP32 evaluation computes every value in FP64 and writes
+  // both copies; the two-index tasks read the FP64 arrays and run in FP64 contraction launches.
+  const bool mixed = p.precision == PS_PREC_MIXED;
+  if (mixed) {
+    const size_t n0 = p.arrays.size();
+    std::vector<char> need32(n0, 0), need64(n0, 0);
+    for (const auto& th : p.tasks) {
+      std::vector<char>& nd = th.out_kind == 4 ? need32 : need64;
+      nd[th.U] = nd[th.V] = nd[th.Y] = 1;
+    }
+    std::vector<int> f64(n0, -1);  // FP64 array holding the values of array a
+    for (size_t a = 0; a < n0; ++a) {
+      if (!need64[a]) continue;
+      if (need32[a]) {
+        ArrayHost t = p.arrays[a];
+        t.es = 8;
+        p.arrays.push_back(t);
+        f64[a] = (int)p.arrays.size() - 1;
+      } else {
+        p.arrays[a].es = 8;
+        f64[a] = (int)a;
+      }
+    }
+    for (auto& th : p.tasks)
+      if (th.out_kind != 4) {
+        th.U = f64[th.U];
+        th.V = f64[th.V];
+        th.Y = f64[th.Y];
+      }
+    for (auto& sg : p.segs) {
+      for (int* a : {&sg.arr0, &sg.arr1}) {
+        int* d = a == &sg.arr0 ? &sg.arr0d : &sg.arr1d;
+        if (*a < 0 || f64[*a] < 0) continue;
+        *d = f64[*a];
+        if (f64[*a] == *a) *a = -1;  // FP64 only
+      }
+    }
+  }
+
   // ---- passes: group grids so that arrays + workspace fit the budget ----
   const TileShape& shape2 = p.tile2;
-  const size_t es = p.elem_size;
   // row tiles of a task: BM consecutive pairs, halved until their staged U + V columns fit
   auto row_tiles = [&](const TaskHost& th, const TileShape& sh) {
     const int BM = sh.bm(), MAXUV = sh.maxuv();
@@ -883,7 +923,7 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
   };
   // per grid: its arrays, and one partial tile per (row tile, column tile) item of its tasks
   std::vector<size_t> grid_bytes(p.grids.size(), 0);
-  for (auto& a : p.arrays) grid_bytes[a.grid] += ((size_t)a.nf * p.grids[a.grid].dev.npad * es + 255) / 256 * 256;
+  for (auto& a : p.arrays) grid_bytes[a.grid] += ((size_t)a.nf * p.grids[a.grid].dev.npad * a.es + 255) / 256 * 256;
   for (auto& th : p.tasks) {
     const TileShape& sh = shape_of(th);
     const size_t items = row_tiles(th, sh).size() * (size_t)((th.dev.ny + sh.bn() - 1) / sh.bn());
@@ -928,7 +968,7 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
     for (auto& a : p.arrays) {
       if (a.grid < ps.grid0 || a.grid >= ps.grid1) continue;
       a.offset = (int64_t)off;
-      off += (size_t)a.nf * p.grids[a.grid].dev.npad * es;
+      off += (size_t)a.nf * p.grids[a.grid].dev.npad * a.es;
       off = (off + 255) / 256 * 256;
     }
     ps.array_bytes = off;
@@ -964,20 +1004,24 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       // groups (one launch each): 0 the main shape, 1 the 64 x 64 shape, 2 + w for w = 1..3 the
       // main shape narrowed to 32 w columns, which takes the last column tile of a main-shape task
       // when that tile is at most 32 w wide (e.g. 345 columns = 128 + 128 + 96 instead of 3 x 128)
-      // (group 5: the 64 x 64 shape narrowed to 32 columns, likewise for its tasks' last tiles)
-      constexpr int NG = 6;
-      TileShape gshape[NG] = {shape, shape2, shape, shape, shape, shape2};
+      // (group 5: the 64 x 64 shape narrowed to 32 columns, likewise for its tasks' last tiles;
+      // groups 6 and 7: the 64 x 64 and 64 x 32 shapes in FP64, for the two-index tasks of a mixed job)
+      constexpr int NG = 8;
+      TileShape gshape[NG] = {shape, shape2, shape, shape, shape, shape2, shape2, shape2};
       for (int w = 1; w <= 3; ++w) {
         gshape[1 + w].wn = w;
         gshape[1 + w].slots = shape.slots_n[w];
       }
       gshape[5].wn = 1;
       gshape[5].slots = shape.slots2n;
+      gshape[6].slots = shape.slots2_f64;
+      gshape[7].wn = 1;
+      gshape[7].slots = shape.slots2n_f64;
       std::vector<Item> items[NG];
-      double total_cost[NG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      double total_cost[NG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       for (int t = ps.task0; t < ps.task1; ++t) {
         TaskHost& th = p.tasks[t];
-        const int grp0 = small_task[t] ? 1 : 0;
+        const int grp0 = (mixed && th.out_kind != 4) ? 6 : (small_task[t] ? 1 : 0);
         const TileShape& sh = gshape[grp0];
         const int BN = sh.bn();
         const int32_t* pr = p.ints.data() + th.pairs_off;
@@ -1007,6 +1051,7 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
             const int w = (it.np + 31) / 32;
             if (grp0 == 0 && w < shape.wn) grp = 1 + w;
             if (grp0 == 1 && w < shape2.wn) grp = 5;
+            if (grp0 == 6 && w < shape2.wn) grp = 7;
             total_cost[grp] += it.cost;
             items[grp].push_back(it);
           }
@@ -1016,10 +1061,11 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       ps.red_by_phase.clear();
       ps.launches.clear();
       ps.tile0 = (int)p.tiles.size();
-      int n_narrow = 0;
-      for (int grp = 2; grp < NG; ++grp) n_narrow += items[grp].empty() ? 0 : 1;
-      // launch order: main, narrow main, 64 x 64, narrow 64 x 64
-      const int order[NG] = {0, 2, 3, 4, 1, 5};
+      int n_narrow = 0, n_second = 0;
+      for (int grp : {2, 3, 4, 5, 7}) n_narrow += items[grp].empty() ? 0 : 1;
+      for (int grp : {1, 6}) n_second += items[grp].empty() ? 0 : 1;
+      // launch order: main, narrow main, 64 x 64, narrow 64 x 64, then the FP64 ones of a mixed job
+      const int order[NG] = {0, 2, 3, 4, 1, 5, 6, 7};
       for (int oi = 0; oi < NG; ++oi) {
         const int grp = order[oi];
         if (items[grp].empty()) continue;
@@ -1030,7 +1076,9 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
         // tile's fixed cost, its first stage and its partial-tile write, stays small against its
         // length); all within the group's workspace reservation (one BM x BN FP64 partial tile per
         // work-group)
-        const size_t cap = grp == 0 ? ws_cap1 : (grp == 1 ? ws_cap2 : ws_cap3 / std::max(1, n_narrow));
+        const size_t cap = grp == 0 ? ws_cap1
+                           : (grp == 1 || grp == 6) ? ws_cap2 / std::max(1, n_second)
+                                                    : ws_cap3 / std::max(1, n_narrow);
         const double ws_tiles = (double)cap / ((double)BM * BN * 8);
         const double want_tiles =
             std::max(2048.0, std::min(6.0 * (double)items[grp].size(), total_cost[grp] / 8192.0));
@@ -1136,7 +1184,7 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
           p.reds.push_back(rd);
         }
         xcd_order(p.tiles, tg0, (int)p.tiles.size());
-        ps.launches.push_back({tg0, (int)p.tiles.size(), sh});
+        ps.launches.push_back({tg0, (int)p.tiles.size(), sh, grp >= 6});
       }
       ps.tile1 = (int)p.tiles.size();
       ps.ws_elems = (size_t)ws;

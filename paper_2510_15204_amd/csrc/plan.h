@@ -21,6 +21,7 @@ struct TileShape {
   int slots2 = 0;                         // the same for the 64 x 64 two-index shape
   int slots_n[4] = {0, 0, 0, 0};          // the same for this shape narrowed to wn = 1..3 (index wn)
   int slots2n = 0;                        // the same for the 64 x 32 shape
+  int slots2_f64 = 0, slots2n_f64 = 0;    // 64 x 64 and 64 x 32 in FP64 within a mixed job
   int bm() const { return 32 * wm; }
   int bn() const { return 32 * wn; }
   int maxuv() const { return bm() + 4; }  // staged U + V columns per tile
@@ -39,6 +40,7 @@ struct GridHost {
 struct ArrayHost {
   int grid;
   int nf;
+  size_t es = 8;        // bytes per element: 8 (FP64) or 4 (FP32 operands of a mixed job)
   int64_t offset;       // bytes from the pass's array region start
   std::vector<int32_t> map;  // column -> caller index (or output selector)
   int64_t map_off;      // int offset in the int table
@@ -46,7 +48,8 @@ struct ArrayHost {
 
 struct SegHost {
   SegDev dev;
-  int arr0, arr1;       // array ids
+  int arr0, arr1;       // array ids (-1: none)
+  int arr0d = -1, arr1d = -1;  // FP64 copies written beside FP32 arr0 / arr1 (mixed jobs)
 };
 
 struct TaskHost {
@@ -68,6 +71,7 @@ struct Pass {
   struct Launch {
     int tile0, tile1;   // consecutive tiles of one contraction launch
     TileShape shape;
+    bool f64 = false;   // FP64 contraction within a mixed job (its two-index tasks)
   };
   std::vector<Launch> launches;  // main shape, 64 x 64 shape, then narrow last-column-tile shapes
   std::vector<std::vector<int>> red_by_phase;  // reduce item ids per phase
@@ -111,7 +115,6 @@ struct Plan {
   size_t max_array_bytes = 0;  // region per pass: arrays, then partial tiles (max over passes)
   size_t max_ws_bytes = 0;     // partial tiles alone (max over passes)
   size_t meta_bytes = 0;
-  size_t elem_size = 8;              // bytes per array element (8 FP64, 4 mixed)
 };
 
 // Validate the job; returns PS_OK or an error code with a message.

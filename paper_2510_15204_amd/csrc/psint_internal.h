@@ -64,8 +64,10 @@ struct WColDev {
 
 // A run of evaluation work: one grid, one centre, a list of shells (sorted by l) or weight columns.
 struct SegDev {
-  void* arr0;         // output array base (double or float per precision)
+  void* arr0;         // output array base (double or float per precision; NULL: none)
   void* arr1;         // second output (EV_CHI_KIN)
+  void* arr0d;        // FP64 copies of arr0 / arr1 written by the FP32 (mixed) evaluation for the
+  void* arr1d;        // two-index contractions, which stay in FP64 (NULL: none)
   int64_t block0;     // first block index of this segment in the launch
   int32_t grid;       // index into the grid table
   int32_t mode;

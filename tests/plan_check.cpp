@@ -66,7 +66,7 @@ int main(int argc, char** argv) {
   TileShape ts;  // the library's defaults: FP64 4 x 4 with 16-point stages, mixed 4 x 4 with 32
   if (job.precision == PS_PREC_MIXED) ts.sc = 2;
   const int slots = atoi(argv[3]);
-  ts.slots = ts.slots2 = ts.slots2n = slots;
+  ts.slots = ts.slots2 = ts.slots2n = ts.slots2_f64 = ts.slots2n_f64 = slots;
   for (int w = 1; w < 4; ++w) ts.slots_n[w] = slots;
   const size_t budget = (size_t)(atof(argv[4]) * 1e9);
   Plan p;

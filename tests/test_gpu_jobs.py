@@ -85,8 +85,9 @@ def test_larger_workloads_sampled_parity(name, prec):
     """The triatomic 5Z job (three refined 128x128x64-point grids, auxiliaries up to l = 6) and the
     hydrocarbon job (252 grids of 64-128 points per axis, several memory passes, contraction launches
     balanced over uneven grids) at full size with the default tiling, as the benchmark runs them,
-    device outputs: sampled elements of every kind against the oracle, within 1e-10 in FP64 and
-    within MIXED_REL_TOL of each type's largest element in mixed precision.  A context of its own,
+    device outputs: sampled elements of every kind against the oracle, within 1e-10 in FP64, and in
+    mixed precision within 1e-10 for S, T, V, (P|Q) and MIXED_ABP_REL_TOL of the largest element for
+    (ab|P).  A context of its own,
     released at the end: the hydrocarbon job reserves most of the device memory."""
     job = getattr(W, name)()
     _say(f"{job.name} {prec}: n_bf={job.n_bf} n_aux={job.n_aux}")
@@ -105,7 +106,7 @@ def test_larger_workloads_sampled_parity(name, prec):
         scale = np.max(np.abs(host[KINDS[k]]))
         e = err[kinds == k].max()
         _say(f"{KINDS[k]}: max abs err {e:.2e} (largest element {scale:.2e})")
-        assert e < (1e-10 if prec == "fp64" else MIXED_REL_TOL * scale), (KINDS[k], e, scale)
+        assert e < (TOL64 if prec == "fp64" else mixed_tol(KINDS[k], scale)), (KINDS[k], e, scale)
     for k in ("S", "T", "V", "PQ"):
         assert np.array_equal(host[k], host[k].T)
 
@@ -146,7 +147,18 @@ def test_multi_panel_cholesky(ctx, device):
     assert np.max(np.abs(L @ L.T - PQ)) < 1e-13 * np.max(np.abs(PQ))
 
 
-MIXED_REL_TOL = 5e-7  # max |GPU mixed - oracle| <= MIXED_REL_TOL * max |oracle| per integral type
+# Mixed precision: S, T, V and (P|Q) are contracted in FP64 inside a mixed job (FP64 copies of their
+# operands), so they meet the FP64 bar.  (ab|P) uses FP32 operands rounded from FP64 values and FP32
+# MFMA sums over 32-point stages folded into FP64: each term carries about one FP32 rounding
+# (2^-24 = 6e-8 relative) per operand and per stage sum, so the error is held to 1e-7 of the type's
+# largest element, under two FP32 units (measured 1.6e-8 to 3.1e-8 on the benchmark jobs, 6.2e-8 on a
+# coarse 8 x 8 x 6-cell grid, where fewer points share each element).
+TOL64 = 1e-10
+MIXED_ABP_REL_TOL = 1e-7
+
+
+def mixed_tol(kind, scale):
+    return MIXED_ABP_REL_TOL * scale if kind == "abP" else TOL64
 
 
 def _tri_tz(spec=(8, 8, 6, 4, 3, 2.3, 0.25)):
@@ -158,8 +170,8 @@ def _tri_tz(spec=(8, 8, 6, 4, 3, 2.3, 0.25)):
 
 @pytest.mark.parametrize("make", ["diatomic", "triatomic_tz"])
 def test_mixed_precision_error_bars(ctx, make):
-    """FP32 values and FP32 MFMA with FP64 flush every 16-point stage: the per-type error stays within
-    5e-7 of each type's largest element (measured 1e-8..2e-6 absolute)."""
+    """Mixed precision against the oracle: S, T, V, (P|Q) and the (P|Q) factor within the FP64 bar
+    (their contractions stay in FP64); (ab|P) within MIXED_ABP_REL_TOL of its largest element."""
     job = W.diatomic_small() if make == "diatomic" else _tri_tz()
     ref = O.compute_full(job)
     got, st, rc = ctx.compute(job, precision="mixed")
@@ -169,8 +181,10 @@ def test_mixed_precision_error_bars(ctx, make):
         em = np.max(np.abs(got[k] - ref[k]))
         e64 = np.max(np.abs(f64[k] - ref[k]))
         _say(f"{make} {k}: mixed {em:.2e} fp64 {e64:.2e} scale {scale:.2e}")
-        assert em <= MIXED_REL_TOL * scale, (k, em, scale)
-        assert e64 < 1e-10
+        assert em <= mixed_tol(k, scale), (k, em, scale)
+        assert e64 < TOL64
+    if rc == 0:
+        assert np.max(np.abs(got["PQ_chol"] - ref["PQ_chol"])) < TOL64 * max(1.0, np.max(np.abs(ref["PQ_chol"])))
 
 
 def _serving_jobs():
