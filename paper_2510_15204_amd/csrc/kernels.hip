@@ -406,9 +406,9 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
   constexpr int NCUV = (MAXUV * SLOTS + 255) / 256;  // copies per thread per stage, U+V region (max)
   constexpr int NCY = (BN * SLOTS + 255) / 256;      // Y region (max)
   constexpr int KSTEPS = KS / 4;
-  // MFMA steps over which the next stage's copies are issued: FP64 steps are long enough to hide them
-  // in the first two; the FP32 steps are half as long, so they spread over all (measured best)
-  constexpr int CSPREAD = (sizeof(T) == 8 && KSTEPS > 2) ? 2 : KSTEPS;
+  // FP64: MFMA steps over which the next stage's copies are issued (steps are long enough to hide
+  // them in the first two); the FP32 paths spread them over all of the stage's step pairs
+  constexpr int CSPREAD = KSTEPS > 2 ? 2 : KSTEPS;
   constexpr bool F64 = sizeof(T) == 8;
   // FP32 tiles of more than 8 blocks per wave: stage sums kept per row block (row-block-outer step
   // order) rather than for the whole tile, which keeps a 4 x 4 tile within two waves per SIMD
@@ -421,6 +421,13 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
   // Rows beyond nrows and columns beyond np are computed on whatever their (in-bounds) LDS rows hold
   // and never read back: an MFMA output row depends only on its A row and an output column only on
   // its B column, and the reduction skips both.  So the operands need no masking.
+  // Points of a stage per MFMA step: FP64, step kk takes point 4 kk + kl from lane group kl; FP32,
+  // steps 2m and 2m + 1 take points 8m + 2 kl and 8m + 2 kl + 1, which one 8-byte LDS read per lane
+  // fetches for both steps (16 rows at the 36-float row stride read 4 bytes per lane fall into the
+  // same LDS bank in pairs, rows j and j + 8; read as 8-byte pairs they do not, and half as many
+  // read instructions move the same bytes).  A and B use the same assignment, so every point enters
+  // every sum once.
+  const int koff = F64 ? kl : 2 * kl;
   int offU[WM], offV[WM];
 #pragma unroll
   for (int mb = 0; mb < WM; ++mb) {
@@ -430,14 +437,14 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
       u = Tk.pairs[2 * (t.row0 + row)];
       v = Tk.pairs[2 * (t.row0 + row) + 1];
     }
-    offU[mb] = (u - t.ulo) * LDK + kl;
-    offV[mb] = (t.nu + v - t.vlo) * LDK + kl;
+    offU[mb] = (u - t.ulo) * LDK + koff;
+    offV[mb] = (t.nu + v - t.vlo) * LDK + koff;
   }
   int offY[WN];
 #pragma unroll
   for (int nb = 0; nb < WN; ++nb) {
     const int col = wn * 16 * WN + nb * 16 + (lane & 15);
-    offY[nb] = (MAXUV + col) * LDK + kl;
+    offY[nb] = (MAXUV + col) * LDK + koff;
   }
 
   const T* __restrict__ Ub = (const T*)Tk.U + (int64_t)t.ulo * KC;
@@ -495,7 +502,6 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
     }
   };
 
-  typedef typename std::conditional<F64, d4_t, f4_t>::type Acc;
   d4_t acc[WM][WN];
 #pragma unroll
   for (int mb = 0; mb < WM; ++mb)
@@ -503,13 +509,27 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
     for (int nb = 0; nb < WN; ++nb) acc[mb][nb] = (d4_t){0.0, 0.0, 0.0, 0.0};
 
   // Operand registers, two slots: the next step's operands are read from LDS while the current
-  // step's MFMAs run.  The first step of stage s + 1 is read right after the barrier that ends
-  // stage s.  In FP64 that barrier sits before the MFMAs of stage s's last step (whose operands are
-  // already in registers), so those MFMAs cover the LDS latency at the stage boundary; FP32 tiles
-  // keep it after the last step (holding the step's FP32 sums across it costs a wave per SIMD).
+  // step's MFMAs run (FP32: the next step pair's).  The first step of stage s + 1 is read right after
+  // the barrier that ends stage s.  In FP64 that barrier sits before the MFMAs of stage s's last step
+  // (whose operands are already in registers), so those MFMAs cover the LDS latency at the stage
+  // boundary; FP32 tiles keep it after the last step pair (measured: holding its FP32 sums and the
+  // next stage's operands across the barrier spills the 4 x 4 tile and slows it by 8%).
   constexpr bool EARLY = F64;
-  T uA[2][WM], vA[2][WM], yB[2][WN];  // whole-tile step order
-  T ru[2], rv[2], ry[2][WN];          // row-block-outer step order
+  T uA[2][WM], vA[2][WM], yB[2][WN];  // FP64 whole-tile step order
+  typedef float f2_t __attribute__((ext_vector_type(2)));
+  typedef const __attribute__((address_space(3))) f2_t* L2p;
+  f2_t uP[2][WM], vP[2][WM], yP[2][WN];  // FP32 whole-tile order, one step pair per slot
+  f2_t ru[2], rv[2], ry[2][WN];          // FP32 row-block-outer order, one step pair per slot
+  // FP32: operands of step pair m (steps 2m, 2m + 1) as 8-byte reads
+  auto fetchp = [&](const __attribute__((address_space(3))) T* cur, int m, int slot) {
+#pragma unroll
+    for (int mb = 0; mb < WM; ++mb) {
+      uP[slot][mb] = *(L2p)(cur + offU[mb] + 8 * m);
+      vP[slot][mb] = *(L2p)(cur + offV[mb] + 8 * m);
+    }
+#pragma unroll
+    for (int nb = 0; nb < WN; ++nb) yP[slot][nb] = *(L2p)(cur + offY[nb] + 8 * m);
+  };
   auto fetch = [&](const __attribute__((address_space(3))) T* cur, int kk, int slot) {
 #pragma unroll
     for (int mb = 0; mb < WM; ++mb) {
@@ -519,12 +539,14 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
 #pragma unroll
     for (int nb = 0; nb < WN; ++nb) yB[slot][nb] = cur[offY[nb] + 4 * kk];
   };
+  // FP32 row-block-outer: iteration it = (row block mb, step pair m)
+  constexpr int NPAIR = KSTEPS / 2;
   auto fetch1 = [&](const __attribute__((address_space(3))) T* cur, int it, int slot) {
-    const int mb = it / KSTEPS, kk = it - mb * KSTEPS;
-    ru[slot] = cur[offU[mb] + 4 * kk];
-    rv[slot] = cur[offV[mb] + 4 * kk];
+    const int mb = it / NPAIR, m = it - mb * NPAIR;
+    ru[slot] = *(L2p)(cur + offU[mb] + 8 * m);
+    rv[slot] = *(L2p)(cur + offV[mb] + 8 * m);
 #pragma unroll
-    for (int nb = 0; nb < WN; ++nb) ry[slot][nb] = cur[offY[nb] + 4 * kk];
+    for (int nb = 0; nb < WN; ++nb) ry[slot][nb] = *(L2p)(cur + offY[nb] + 8 * m);
   };
   // FP64, before the last step's MFMAs of stage s (uniform): wait for this wave's copies of stage
   // s + 1, barrier, then read the first operands of stage s + 1 into slot 0
@@ -560,26 +582,30 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
       // FP32: one row block at a time over the stage's steps, so only WN blocks of FP32 stage sums
       // are live; they go into the FP64 accumulators after the row block's last step.  The Y
       // operands are read from LDS once per row block.
-      constexpr int NIT = WM * KSTEPS;
+      constexpr int NIT = WM * NPAIR;
       fetch1(cur, 0, 0);
       f4_t s32[WN];
 #pragma unroll
       for (int it = 0; it < NIT; ++it) {
-        const int mb = it / KSTEPS, kk = it - mb * KSTEPS, sl = it & 1;
+        const int m = it % NPAIR, sl = it & 1;
         if (it + 1 < NIT) fetch1(cur, it + 1, sl ^ 1);
-        const T av = ru[sl] * rv[sl];
-        T bv[WN];
+        const float av0 = ru[sl].x * rv[sl].x, av1 = ru[sl].y * rv[sl].y;
+        f2_t bv[WN];
 #pragma unroll
         for (int nb = 0; nb < WN; ++nb) bv[nb] = ry[sl][nb];
 #pragma unroll
         for (int nb = 0; nb < WN; ++nb)
-          s32[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[nb], kk == 0 ? f4_t{} : s32[nb], 0, 0, 0);
+          s32[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av0, bv[nb].x, m == 0 ? f4_t{} : s32[nb], 0, 0, 0);
+#pragma unroll
+        for (int nb = 0; nb < WN; ++nb)
+          s32[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av1, bv[nb].y, s32[nb], 0, 0, 0);
         if (more) {
 #pragma unroll
           for (int i = 0; i < NCUV + NCY; ++i)
             if (i % NIT == it) copy(s + 1, i);
         }
-        if (kk == KSTEPS - 1) {
+        if (m == NPAIR - 1) {
+          const int mb = it / NPAIR;
 #pragma unroll
           for (int nb = 0; nb < WN; ++nb)
 #pragma unroll
@@ -589,14 +615,48 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
       stage_end();
       return;
     }
-    if constexpr (!EARLY) fetch(cur, 0, 0);
-    Acc a32[WM][WN];
     if constexpr (!F64) {
+      // FP32 whole tile, one step pair per iteration
+      fetchp(cur, 0, 0);
+      f4_t a32[WM][WN];
 #pragma unroll
       for (int mb = 0; mb < WM; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < WN; ++nb) a32[mb][nb] = Acc{};
+        for (int nb = 0; nb < WN; ++nb) a32[mb][nb] = f4_t{};
+#pragma unroll
+      for (int m = 0; m < NPAIR; ++m) {
+        const int sl = m & 1;
+        if (m + 1 < NPAIR) fetchp(cur, m + 1, sl ^ 1);
+        float av[2][WM];
+#pragma unroll
+        for (int mb = 0; mb < WM; ++mb) {
+          av[0][mb] = uP[sl][mb].x * vP[sl][mb].x;
+          av[1][mb] = uP[sl][mb].y * vP[sl][mb].y;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int mb = 0; mb < WM; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < WN; ++nb)
+              a32[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[h][mb], h ? yP[sl][nb].y : yP[sl][nb].x,
+                                                                 a32[mb][nb], 0, 0, 0);
+        if (more) {
+#pragma unroll
+          for (int i = 0; i < NCUV + NCY; ++i)
+            if (i % NPAIR == m) copy(s + 1, i);
+        }
+      }
+#pragma unroll
+      for (int mb = 0; mb < WM; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < WN; ++nb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[mb][nb][r] += (double)a32[mb][nb][r];
+      stage_end();
+      return;
     }
+    // FP64: one step per iteration
 #pragma unroll
     for (int kk = 0; kk < KSTEPS; ++kk) {
       const int sl = kk & 1;
@@ -606,16 +666,12 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
       for (int mb = 0; mb < WM; ++mb) av[mb] = uA[sl][mb] * vA[sl][mb];
 #pragma unroll
       for (int nb = 0; nb < WN; ++nb) bv[nb] = yB[sl][nb];
-      if (EARLY && kk + 1 == KSTEPS && more) boundary(s);
+      if (kk + 1 == KSTEPS && more) boundary(s);
 #pragma unroll
       for (int mb = 0; mb < WM; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < WN; ++nb) {
-          if constexpr (F64)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
-          else
-            a32[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb], bv[nb], a32[mb][nb], 0, 0, 0);
-        }
+        for (int nb = 0; nb < WN; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
       // the next stage's copies, spread over the steps (into the other buffer)
       if (more) {
 #pragma unroll
@@ -623,16 +679,6 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
           if (i % CSPREAD == kk) copy(s + 1, i);
       }
     }
-    if constexpr (!F64) {
-      // flush this stage's FP32 partial sums into the FP64 accumulators
-#pragma unroll
-      for (int mb = 0; mb < WM; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < WN; ++nb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc[mb][nb][r] += (double)a32[mb][nb][r];
-    }
-    if constexpr (!EARLY) stage_end();
   };
   for (int s = 0; s < nstage; ++s) run_stage(s);
   double* __restrict__ wt = ws + t.ws;
