@@ -50,7 +50,7 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
   do {                                                                                       \
     hipError_t e_ = (call);                                                                  \
     if (e_ != hipSuccess) {                                                                  \
-      ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);                          \
+      set_err(ctx, std::string(#call) + ": " + hipGetErrorString(e_));                       \
       return PS_E_DEVICE;                                                                    \
     }                                                                                        \
   } while (0)
@@ -135,6 +135,11 @@ void pool_destroy(ps_ctx* ctx) {
   P.total = 0;
 }
 
+void set_err(ps_ctx* ctx, const std::string& msg) {
+  std::lock_guard<std::mutex> g(ctx->err_mu);
+  ctx->err = msg;
+}
+
 int32_t ensure_arena(ps_ctx* ctx, Slot& s, size_t bytes) {
   if (s.arena_size >= bytes) return PS_OK;
   if (s.arena) {
@@ -145,11 +150,16 @@ int32_t ensure_arena(ps_ctx* ctx, Slot& s, size_t bytes) {
   s.arena_size = 0;
   size_t got = 0;
   void* p = pool_alloc(ctx, bytes, &got);
+  if (!p && &s == &ctx->sync_slot) {
+    // the synchronous slot (caller holds sync_mu): idle serving slots give their ranges back
+    release_idle_serve_arenas(ctx);
+    p = pool_alloc(ctx, bytes, &got);
+  }
   if (!p) {
     char buf[160];
     snprintf(buf, sizeof buf, "no device memory for a %.2f GB arena within the %.2f GB budget", bytes / 1e9,
              ctx->budget / 1e9);
-    ctx->err = buf;
+    set_err(ctx, buf);
     return PS_E_NOMEM;
   }
   s.arena = p;
@@ -424,7 +434,7 @@ int32_t plan_job(ps_ctx* ctx, const ps_job* job, Plan& plan, Layout& L) {
   std::string err;
   int32_t rc = build_plan(job, effective_shape(ctx, job->precision), ctx->ksplit, ctx->budget, &plan, &err);
   if (rc) {
-    ctx->err = err;
+    set_err(ctx, err);
     return rc;
   }
   compute_layout(plan, L);
@@ -432,7 +442,7 @@ int32_t plan_job(ps_ctx* ctx, const ps_job* job, Plan& plan, Layout& L) {
     char buf[200];
     snprintf(buf, sizeof buf, "job needs %.2f GB of device memory, budget is %.2f GB", L.total / 1e9,
              ctx->budget / 1e9);
-    ctx->err = buf;
+    set_err(ctx, buf);
     return PS_E_NOMEM;
   }
   return PS_OK;
@@ -486,7 +496,7 @@ int32_t finish_stats(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, ps_jo
     st->queue_ms = queue_ms;
   }
   if (s.want_chol && status) {
-    ctx->err = "(P|Q) is not positive definite";
+    set_err(ctx, "(P|Q) is not positive definite");
     return PS_E_NOT_PD;
   }
   return PS_OK;
@@ -540,8 +550,16 @@ const char* ps_status_string(int32_t status) {
 }
 
 const char* ps_last_error(ps_ctx* ctx) {
-  static thread_local std::string none = "";
-  return ctx ? ctx->err.c_str() : none.c_str();
+  // a copy per calling thread, taken under the context's lock: the text stays valid until this
+  // thread's next ps_last_error call, whatever other threads do on the context meanwhile
+  static thread_local std::string copy;
+  if (!ctx) {
+    copy.clear();
+    return copy.c_str();
+  }
+  std::lock_guard<std::mutex> g(ctx->err_mu);
+  copy = ctx->err;
+  return copy.c_str();
 }
 
 int32_t ps_create(int32_t hip_device, size_t hbm_budget_bytes, void* stream, ps_ctx** out) {
@@ -583,7 +601,7 @@ int32_t ps_destroy(ps_ctx* ctx) {
 int32_t ps_mfma_rate(ps_ctx* ctx, int32_t precision, double* tflops) {
   if (!ctx) return PS_E_INVALID;
   if (!tflops || (precision != PS_PREC_FP64 && precision != PS_PREC_MIXED)) {
-    ctx->err = "mfma_rate: tflops must be given, precision PS_PREC_FP64 or PS_PREC_MIXED";
+    set_err(ctx, "mfma_rate: tflops must be given, precision PS_PREC_FP64 or PS_PREC_MIXED");
     return PS_E_INVALID;
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
@@ -596,7 +614,7 @@ int32_t ps_mfma_rate(ps_ctx* ctx, int32_t precision, double* tflops) {
   size_t got = 0;
   double* out = (double*)pool_alloc(ctx, (size_t)blocks * 4 * sizeof(double), &got);
   if (!out) {
-    ctx->err = "mfma_rate: no device memory for the probe's output";
+    set_err(ctx, "mfma_rate: no device memory for the probe's output");
     return PS_E_NOMEM;
   }
   hipStream_t st = ctx->sync_slot.stream;
@@ -614,7 +632,7 @@ int32_t ps_mfma_rate(ps_ctx* ctx, int32_t precision, double* tflops) {
     if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = PS_E_DEVICE;
     if (rep > 0 && (best_ms == 0.0 || ms < best_ms)) best_ms = ms;
   }
-  if (rc != PS_OK) ctx->err = std::string("mfma_rate: ") + hipGetErrorString(hipGetLastError());
+  if (rc != PS_OK) set_err(ctx, std::string("mfma_rate: ") + hipGetErrorString(hipGetLastError()));
   (void)hipStreamSynchronize(st);
   pool_release(ctx, out, got);
   if (e0) (void)hipEventDestroy(e0);
@@ -627,7 +645,7 @@ int32_t ps_set_tiling(ps_ctx* ctx, int32_t wm, int32_t wn, int32_t stage_chunks,
   if (!ctx) return PS_E_INVALID;
   if (wm == 0 && wn == 0 && stage_chunks == 0) {
     if (ksplit < 0) {
-      ctx->err = "tiling: ksplit >= 0";
+      set_err(ctx, "tiling: ksplit >= 0");
       return PS_E_INVALID;
     }
     ctx->shape_explicit = false;  // the default shape of each job's precision
@@ -640,7 +658,7 @@ int32_t ps_set_tiling(ps_ctx* ctx, int32_t wm, int32_t wn, int32_t stage_chunks,
   if (wn == 0) wn = def.wn;
   if (stage_chunks == 0) stage_chunks = def.sc;
   if (!((wm == 2 || wm == 4) && (wn == 2 || wn == 4) && (stage_chunks == 1 || stage_chunks == 2)) || ksplit < 0) {
-    ctx->err = "tiling: wm, wn in {2, 4}, stage_chunks in {1, 2}, ksplit >= 0";
+    set_err(ctx, "tiling: wm, wn in {2, 4}, stage_chunks in {1, 2}, ksplit >= 0");
     return PS_E_INVALID;
   }
   ctx->shape.wm = wm;
@@ -750,7 +768,7 @@ int32_t ps_plan_work(ps_ctx* ctx, const ps_job* job, double* pair_points, int64_
   TileShape shape = effective_shape(ctx, job->precision);
   int32_t rc = build_plan(job, shape, ctx ? ctx->ksplit : 0, ctx ? ctx->budget : ((size_t)1 << 62), &plan, &err);
   if (rc) {
-    if (ctx) ctx->err = err;
+    if (ctx) set_err(ctx, err);
     return rc;
   }
   Layout L;
@@ -769,7 +787,7 @@ int32_t ps_grid_points(ps_ctx* ctx, const ps_atom* atoms, int32_t n_atoms, int32
   std::string err;
   int32_t rc = build_grid(atoms, n_atoms, A, B, C, *spec, &g, &err);
   if (rc) {
-    ctx->err = err;
+    set_err(ctx, err);
     return rc;
   }
   *n_points = g.dev.npts;
@@ -791,7 +809,7 @@ int32_t ps_grid_points(ps_ctx* ctx, const ps_atom* atoms, int32_t n_atoms, int32
   hipError_t e = hipMalloc(&dp, (size_t)g.dev.npts * 4 * 8);
   if (e != hipSuccess) {
     (void)hipFree(dl);
-    ctx->err = hipGetErrorString(e);
+    set_err(ctx, hipGetErrorString(e));
     return PS_E_DEVICE;
   }
   e = hipMemcpyAsync(dl, lines.data(), lines.size() * 8, hipMemcpyHostToDevice, st);
@@ -801,7 +819,7 @@ int32_t ps_grid_points(ps_ctx* ctx, const ps_atom* atoms, int32_t n_atoms, int32
   (void)hipFree(dl);
   (void)hipFree(dp);
   if (e != hipSuccess) {
-    ctx->err = hipGetErrorString(e);
+    set_err(ctx, hipGetErrorString(e));
     return PS_E_DEVICE;
   }
   return PS_OK;
@@ -841,7 +859,7 @@ int32_t ps_eval_function(ps_ctx* ctx, int32_t what, const ps_sto* fn, const doub
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(d);
   if (e != hipSuccess) {
-    ctx->err = hipGetErrorString(e);
+    set_err(ctx, hipGetErrorString(e));
     return PS_E_DEVICE;
   }
   return PS_OK;

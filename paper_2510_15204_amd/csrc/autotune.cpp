@@ -31,7 +31,7 @@ int32_t time_candidate(ps_ctx* ctx, const ps_job* job, int reps, ps_tuning* out)
     if (rc) return rc;
     hipError_t e = hipStreamSynchronize(s.stream);
     if (e != hipSuccess) {
-      ctx->err = std::string("autotune: ") + hipGetErrorString(e);
+      set_err(ctx, std::string("autotune: ") + hipGetErrorString(e));
       return PS_E_DEVICE;
     }
     ps_job_stats st;
@@ -50,7 +50,7 @@ extern "C" int32_t ps_autotune(ps_ctx* ctx, const ps_job* job, int32_t reps, ps_
                                int32_t max_table, int32_t* n_table) {
   if (!ctx) return PS_E_INVALID;
   if (!job || !best || reps < 1 || (max_table > 0 && !table)) {
-    ctx->err = "autotune: job and best must be given, reps >= 1";
+    set_err(ctx, "autotune: job and best must be given, reps >= 1");
     return PS_E_INVALID;
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
@@ -100,7 +100,7 @@ extern "C" int32_t ps_autotune(ps_ctx* ctx, const ps_job* job, int32_t reps, ps_
     if (rc != PS_OK) {  // this shape's workspace does not fit the budget: skip it
       if (first_err == PS_OK) {
         first_err = rc;
-        first_msg = ctx->err;
+        first_msg = ps_last_error(ctx);
       }
       continue;
     }
@@ -113,7 +113,7 @@ extern "C" int32_t ps_autotune(ps_ctx* ctx, const ps_job* job, int32_t reps, ps_
     ctx->shape = saved;
     ctx->shape_explicit = saved_explicit;
     ctx->ksplit = saved_ksplit;
-    ctx->err = first_msg;
+    set_err(ctx, first_msg);
     return first_err;
   }
   ctx->shape.wm = win.wm;

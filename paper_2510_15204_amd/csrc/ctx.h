@@ -73,7 +73,8 @@ struct ps_ctx {
   int device = 0;
   size_t budget = 0;
   hipStream_t user_stream = nullptr;
-  std::string err;
+  std::string err;     // last error text: written through set_err, read by ps_last_error (err_mu)
+  std::mutex err_mu;
   psint::TileShape shape;
   bool shape_explicit = false;  // false: the default shape of the job's precision
   int ksplit = 0;
@@ -81,7 +82,8 @@ struct ps_ctx {
   std::mutex sync_mu;  // held while ps_compute / ps_autotune use sync_slot; the serving dispatcher
                        // takes an idle sync_slot's arena back when a queued job needs the memory
   std::atomic<size_t> sync_arena_bytes{0};  // sync_slot.arena_size as last published under sync_mu
-  psint::ServeState* serve = nullptr;  // created by the first ps_submit, freed by ps_destroy
+  std::atomic<psint::ServeState*> serve{nullptr};  // created by the first ps_submit (under
+  std::mutex serve_init_mu;                       // serve_init_mu), freed by ps_destroy
   psint::DevicePool pool;              // slot arenas
 };
 
@@ -98,5 +100,10 @@ void pool_release(ps_ctx* ctx, void* p, size_t bytes);
 void pool_destroy(ps_ctx* ctx);
 // Looks up the allocation-free RI entry point's static scratch address on `device` (current).
 int32_t ri_noalloc_init(int device);
+// Records the context's last error text (serving and synchronous calls may overlap).
+void set_err(ps_ctx* ctx, const std::string& msg);
+// Synchronous calls that find no room in the pool: the ranges kept by idle serving slots go back to
+// it.  Called with sync_mu held (the serving dispatcher only try-locks sync_mu).
+void release_idle_serve_arenas(ps_ctx* ctx);
 
 }  // namespace psint

@@ -415,7 +415,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
   do {                                                            \
     hipError_t e_ = (call);                                       \
     if (e_ != hipSuccess) {                                       \
-      ctx->err = std::string(#call) + ": " + hipGetErrorString(e_); \
+      set_err(ctx, std::string(#call) + ": " + hipGetErrorString(e_)); \
       return PS_E_DEVICE;                                         \
     }                                                             \
   } while (0)
@@ -424,7 +424,7 @@ extern "C" int32_t ps_ri_assemble(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, int3
                                   const double* L, double* B, double* eri, double* device_ms) {
   if (!ctx) return PS_E_INVALID;
   if (n_bf < 1 || n_aux < 1 || !abP || !L || (location != PS_OUT_HOST && location != PS_OUT_DEVICE)) {
-    ctx->err = "ri: n_bf, n_aux >= 1, abP and L required, location PS_OUT_HOST or PS_OUT_DEVICE";
+    set_err(ctx, "ri: n_bf, n_aux >= 1, abP and L required, location PS_OUT_HOST or PS_OUT_DEVICE");
     return PS_E_INVALID;
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
@@ -458,7 +458,7 @@ extern "C" int32_t ps_ri_assemble(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, int3
   if (total > ctx->budget) {
     char buf[160];
     snprintf(buf, sizeof buf, "ri: needs %.2f GB of device memory, budget is %.2f GB", total / 1e9, ctx->budget / 1e9);
-    ctx->err = buf;
+    set_err(ctx, buf);
     return PS_E_NOMEM;
   }
   hipStream_t st = ctx->sync_slot.stream;
@@ -471,10 +471,15 @@ extern "C" int32_t ps_ri_assemble(ps_ctx* ctx, int32_t n_bf, int32_t n_aux, int3
     scratch.p = pool_alloc(ctx, total, &scratch.size);
   }
   if (!scratch.p) {
+    // then the ranges idle serving slots keep
+    release_idle_serve_arenas(ctx);
+    scratch.p = pool_alloc(ctx, total, &scratch.size);
+  }
+  if (!scratch.p) {
     char buf[160];
     snprintf(buf, sizeof buf, "ri: no device memory for %.2f GB of scratch within the %.2f GB budget", total / 1e9,
              ctx->budget / 1e9);
-    ctx->err = buf;
+    set_err(ctx, buf);
     return PS_E_NOMEM;
   }
   char* base = (char*)scratch.p;
@@ -559,7 +564,7 @@ extern "C" int32_t ps_ri_assemble_noalloc(ps_ctx* ctx, int32_t n_bf, int32_t n_a
                                           const double* L, double* B, double* eri) {
   if (!ctx) return PS_E_INVALID;
   if (n_bf < 1 || n_aux < 1 || !abP || !L) {
-    ctx->err = "ri (no-alloc): n_bf, n_aux >= 1, abP and L required";
+    set_err(ctx, "ri (no-alloc): n_bf, n_aux >= 1, abP and L required");
     return PS_E_INVALID;
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return PS_E_DEVICE;
@@ -582,7 +587,7 @@ extern "C" int32_t ps_ri_assemble_noalloc(ps_ctx* ctx, int32_t n_bf, int32_t n_a
     snprintf(buf, sizeof buf,
              "ri (no-alloc): needs %.1f MiB of scratch (n_aux %d, n_pair %lld%s), the static scratch holds %.1f MiB",
              total / 1048576.0, n_aux, (long long)npair, B ? "" : ", B not given", PS_RI_NOALLOC_SCRATCH_BYTES / 1048576.0);
-    ctx->err = buf;
+    set_err(ctx, buf);
     return PS_E_NOMEM;
   }
   void* base_v = nullptr;

@@ -95,7 +95,7 @@ static void finish_ticket(ps_ctx* ctx, ServeState& S, int si) {
 }
 
 static void worker_loop(ps_ctx* ctx) {
-  ServeState& S = *ctx->serve;
+  ServeState& S = *ctx->serve.load();
   (void)hipSetDevice(ctx->device);
   std::unique_lock<std::mutex> lk(S.mu);
   while (true) {
@@ -109,7 +109,7 @@ static void worker_loop(ps_ctx* ctx) {
         any_done = true;
       } else if (q != hipErrorNotReady) {
         S.running[si]->status = PS_E_DEVICE;
-        ctx->err = std::string("serving: ") + hipGetErrorString(q);
+        set_err(ctx, std::string("serving: ") + hipGetErrorString(q));
         finish_ticket(ctx, S, si);
         any_done = true;
       }
@@ -212,7 +212,9 @@ static void worker_loop(ps_ctx* ctx) {
 }
 
 static int32_t serve_start(ps_ctx* ctx) {
-  if (ctx->serve) return PS_OK;
+  if (ctx->serve.load()) return PS_OK;
+  std::lock_guard<std::mutex> g(ctx->serve_init_mu);
+  if (ctx->serve.load()) return PS_OK;
   ServeState* st = new ServeState();
   st->slots.resize(kMaxSlots);
   st->running.resize(kMaxSlots);
@@ -224,22 +226,35 @@ static int32_t serve_start(ps_ctx* ctx) {
       return rc;
     }
   }
-  ctx->serve = st;
-  ctx->serve->worker = std::thread(worker_loop, ctx);
+  ctx->serve.store(st);
+  st->worker = std::thread(worker_loop, ctx);
   return PS_OK;
 }
 
 void serve_shutdown(ps_ctx* ctx) {
-  if (!ctx->serve) return;
+  ServeState* st = ctx->serve.load();
+  if (!st) return;
   {
-    std::lock_guard<std::mutex> g(ctx->serve->mu);
-    ctx->serve->stop = true;
+    std::lock_guard<std::mutex> g(st->mu);
+    st->stop = true;
   }
-  ctx->serve->cv_work.notify_all();
-  if (ctx->serve->worker.joinable()) ctx->serve->worker.join();
-  for (auto& s : ctx->serve->slots) slot_free(ctx, s);
-  delete ctx->serve;
-  ctx->serve = nullptr;
+  st->cv_work.notify_all();
+  if (st->worker.joinable()) st->worker.join();
+  for (auto& s : st->slots) slot_free(ctx, s);
+  ctx->serve.store(nullptr);
+  delete st;
+}
+
+void release_idle_serve_arenas(ps_ctx* ctx) {
+  ServeState* st = ctx->serve.load();
+  if (!st) return;
+  std::lock_guard<std::mutex> g(st->mu);
+  for (int si = 0; si < (int)st->slots.size(); ++si)
+    if (!st->running[si] && st->slots[si].arena) {
+      pool_release(ctx, st->slots[si].arena, st->slots[si].arena_size);
+      st->slots[si].arena = nullptr;
+      st->slots[si].arena_size = 0;
+    }
 }
 
 }  // namespace psint
@@ -259,7 +274,7 @@ int32_t ps_submit(ps_ctx* ctx, const ps_job* job, uint64_t* ticket) {
   t->need_bytes = t->layout.total;
   rc = serve_start(ctx);
   if (rc) return rc;
-  ServeState& S = *ctx->serve;
+  ServeState& S = *ctx->serve.load();
   {
     std::lock_guard<std::mutex> g(S.mu);
     if (S.queue.size() >= kMaxQueue) return PS_E_QUEUE_FULL;
@@ -274,8 +289,9 @@ int32_t ps_submit(ps_ctx* ctx, const ps_job* job, uint64_t* ticket) {
 
 int32_t ps_wait(ps_ctx* ctx, uint64_t ticket, int64_t timeout_us, ps_job_stats* st) {
   if (!ctx) return PS_E_INVALID;
-  if (!ctx->serve) return PS_E_NOT_FOUND;
-  ServeState& S = *ctx->serve;
+  ServeState* sp = ctx->serve.load();
+  if (!sp) return PS_E_NOT_FOUND;
+  ServeState& S = *sp;
   std::unique_lock<std::mutex> lk(S.mu);
   auto it = S.tickets.find(ticket);
   if (it == S.tickets.end()) return PS_E_NOT_FOUND;

@@ -326,6 +326,47 @@ def test_device_pool_reuse_across_job_sizes():
     c.close()
 
 
+def test_compute_after_serving_takes_back_idle_slot_memory():
+    """A served job leaves its arena with its (now idle) serving slot.  A later ps_compute of another
+    job on the same context, which fits the budget only with that memory, takes it back from the slot
+    instead of failing, and so does an RI call after serving again; results equal those of a fresh
+    context with the same budget."""
+    a = _tri_tz((8, 8, 6, 4, 3, 2.3, 0.25))
+    b = _tri_tz((9, 8, 6, 4, 3, 2.3, 0.25))
+    # a budget that holds either job's device memory but not both (the plan's workspace depends on
+    # the budget, so the needs are taken from the planner under that budget)
+    budget = psint.plan_work_host(a)["device_bytes"]
+    for _ in range(6):
+        probe = psint.Context(0, budget_bytes=budget)
+        na_, nb_ = probe.plan_work(a)["device_bytes"], probe.plan_work(b)["device_bytes"]
+        probe.close()
+        mib = 2 << 20
+        ra, rb = -(-na_ // mib) * mib, -(-nb_ // mib) * mib  # pool ranges are 2 MiB multiples
+        if max(ra, rb) + mib <= budget < ra + rb:
+            break
+        budget = int(1.3 * max(ra, rb)) + mib
+    _say(f"needs {na_ / 1e6:.0f} / {nb_ / 1e6:.0f} MB, budget {budget / 1e6:.0f} MB")
+    assert max(ra, rb) + mib <= budget < ra + rb
+    rng = np.random.default_rng(3)
+    M = rng.normal(size=(len(b.aux),) * 2)
+    Lr = np.linalg.cholesky(M @ M.T + len(b.aux) * np.eye(len(b.aux)))  # any factor: RI is linear in it
+    fresh = psint.Context(0, budget_bytes=budget)  # same budget: same plan, same summation order
+    ref_b, _, _ = fresh.compute(b)
+    B_ref, e_ref, _ = fresh.ri_assemble(ref_b["abP"], Lr)
+    fresh.close()
+    c = psint.Context(0, budget_bytes=budget)
+    try:
+        c.wait(c.submit(a))
+        got, _, rc = c.compute(b)
+        for k in psint.OUTPUTS:
+            assert np.array_equal(got[k], ref_b[k]), k
+        c.wait(c.submit(a))
+        B, e, _ = c.ri_assemble(got["abP"], Lr)
+        assert np.array_equal(B, B_ref) and np.array_equal(e, e_ref)
+    finally:
+        c.close()
+
+
 def test_autotune_selects_fastest_and_keeps_results():
     """ps_autotune times every candidate tiling, leaves the fastest on the context, and a job run with
     it agrees with the default tiling (up to the summation order of the point splits) and the oracle."""

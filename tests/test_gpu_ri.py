@@ -159,12 +159,14 @@ def test_ri_end_to_end_closed_forms(ctx):
     assert abs(eri[aa, bb] - J) < 1e-8
 
 
-@pytest.mark.parametrize("nb,na", [(1, 1), (2, 33), (11, 64), (12, 65), (20, 97), (5, 1024), (5, 1025)])
+@pytest.mark.parametrize("nb,na", [(1, 1), (2, 33), (11, 64), (12, 65), (20, 97), (5, 1024), (5, 1025), (65, 33),
+                                   (130, 40)])
 def test_ri_edge_sizes(ctx, nb, na):
-    """Single pair / single auxiliary function, one-past-a-block sizes, several 16-pair strips, and
-    the largest n_aux the one-launch substitution holds in LDS (1024) and the first beyond it (one
-    launch per block step): random SPD factor and random (ab|P) symmetric in a, b, compared with
-    the oracle."""
+    """Single pair / single auxiliary function, one-past-a-block sizes, several 16-pair strips, the
+    largest n_aux the one-launch substitution holds in LDS (1024) and the first beyond it (one launch
+    per block step), and n_bf 65 and 130, whose rows a >= 64 take the gather's second lap of 64 lanes
+    (one wave per row of (ab|P)): random SPD factor and random (ab|P) symmetric in a, b, compared
+    with the oracle."""
     rng = np.random.default_rng(nb * 100 + na)
     M = rng.normal(size=(na, na))
     L = np.linalg.cholesky(M @ M.T + na * np.eye(na))
