@@ -434,6 +434,19 @@ def serve_bench(args, torch, psint, W):
     makespan = t_end - t0
     lat = np.array([(d[0] - a) * 1e3 for d, a in ok])
     pp = sum(d[1]["pair_points"] for d, _ in ok)
+    # in service = admitted on the device -> results ready; busy = union of those intervals
+    spans = sorted((a + d[1]["queue_ms"] / 1e3, a + d[1]["total_ms"] / 1e3) for d, a in ok)
+    busy, cur0, cur1 = 0.0, None, None
+    for b0, b1 in spans:
+        if cur1 is None or b0 > cur1:
+            if cur1 is not None:
+                busy += cur1 - cur0
+            cur0, cur1 = b0, b1
+        else:
+            cur1 = max(cur1, b1)
+    if cur1 is not None:
+        busy += cur1 - cur0
+    service_ms = [d[1]["total_ms"] - d[1]["queue_ms"] for d, _ in ok]
     done = [d for d, _ in ok]
     atoms = [job.n_atoms for _, job in meas]
     out = {"metric": "S/T/V/(ab|P) quadrature pair·points/s at stated error vs FP64; p99 job latency",
@@ -446,9 +459,12 @@ def serve_bench(args, torch, psint, W):
                       "pair_points_total": pp},
            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                           "max": float(lat.max())},
-           "serving": {"makespan_s": makespan, "capacity_requests_per_s": n_meas / makespan,
-                       "offered_load": args.rate * makespan / n_meas,
+           "serving": {"makespan_s": makespan, "completed_requests_per_s": n_meas / makespan,
                        "mean_queue_ms": float(np.mean([d[1]["queue_ms"] for d in done])),
+                       "mean_service_ms": float(np.mean(service_ms)),
+                       "utilisation_rho": args.rate * float(np.mean(service_ms)) / 1e3,
+                       "device_busy_fraction": busy / makespan,
+                       "latency_ms_each": [round(float(x), 1) for x in lat],
                        "not_pd": int(sum(d[2] == psint.PS_E_NOT_PD for d in done)), "rejected": rejected}}
     print(json.dumps(out), flush=True)
 

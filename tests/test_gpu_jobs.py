@@ -221,7 +221,39 @@ def test_serving_results_identical_alone_and_in_the_mix(ctx, prec):
             assert np.array_equal(out[k], a[k]), k
         assert st["total_ms"] >= st["queue_ms"] >= 0.0
     ref = O.compute_full(jobs[1])
-    assert np.max(np.abs(alone[1]["abP"] - ref["abP"])) < (1e-10 if prec == "fp64" else 1e-5)
+    for k in KINDS:
+        scale = float(np.max(np.abs(ref[k])))
+        tol = TOL64 if prec == "fp64" else mixed_tol(k, scale)
+        assert np.max(np.abs(alone[1][k] - ref[k])) < tol, k
+
+
+SERVING_PICKS = [2, 5, 9, 12, 19, 31]  # requests of 2-4 atoms with DZ/TZ-sized bases, 0.4-8.5 M points
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_serving_stream_requests_identical_alone_and_in_the_mix(ctx, prec):
+    """Six requests of the serving stream itself (random tree-grown molecules of 2-4 atoms, DZ/TZ-sized
+    bases with 3x auxiliary sets, per-pair grids of 48-128 points per axis) submitted together: each
+    result equals the request run alone bit for bit, and sampled elements of every kind match the
+    oracle (FP64: 1e-10; mixed: S, T, V, (P|Q) 1e-10, (ab|P) MIXED_ABP_REL_TOL of its largest)."""
+    reqs = W.serving_stream(n_requests=max(SERVING_PICKS) + 1)
+    jobs = [reqs[i][1] for i in SERVING_PICKS]
+    _say(", ".join(f"{j.name} ({j.n_bf}/{j.n_aux})" for j in jobs))
+    alone = [ctx.compute(j, precision=prec)[0] for j in jobs]
+    handles = [ctx.submit(j, precision=prec) for j in jobs]
+    for h, a in zip(handles, alone):
+        out, st, rc = ctx.wait(h, timeout_us=120_000_000)
+        assert rc in (psint.PS_OK, psint.PS_E_NOT_PD)
+        for k in psint.OUTPUTS:
+            assert np.array_equal(out[k], a[k]), k
+    for t, (j, a) in enumerate(zip(jobs, alone)):
+        kinds, I, J, K = sample(j, 12, 100 + t)
+        ref, _ = O.compute_elements(j, kinds, I, J, K)
+        err = np.abs(pick(a, kinds, I, J, K) - ref)
+        for kd in range(5):
+            name = KINDS[kd]
+            tol = TOL64 if prec == "fp64" else mixed_tol(name, float(np.max(np.abs(a[name]))))
+            assert err[kinds == kd].max() < tol, (j.name, name, err[kinds == kd].max())
 
 
 def test_serving_device_outputs_and_stats(ctx):
