@@ -171,6 +171,17 @@ int32_t ps_plan_work(ps_ctx* ctx, const ps_job* job, double* pair_points, int64_
  * context when the job's inputs, the tiling and the budget are unchanged. */
 int32_t ps_set_tiling(ps_ctx* ctx, int32_t wm, int32_t wn, int32_t stage_chunks, int32_t ksplit);
 
+/* Context options for later jobs.  PS_OPT_SHARE_THIRD_CENTRE (value -1 = automatic, the default: on
+ * for FP64 jobs, off for mixed ones; 0 = off; 1 = on): cross-third-centre reuse of basis values.  The grids G(A,B|C) of one atom pair, other than its pair
+ * grid, differ only by a rotation about the A-B axis (each places its C at phi = 0, Section 2.3) and
+ * by the lines moved onto their C (Section 2.2); in the regular cells that no such grid's moved lines
+ * touch their points share (mu, nu, phi) and the distances to A and B.  With the option on, the
+ * radial factors of A's and B's functions there are computed once for all of those grids and only
+ * the angular factors per grid (grids with Q = 4 and at most 128 cells per axis, all of one pair in
+ * one memory pass).  Results are unchanged to rounding.  PS_E_INVALID for other options or values. */
+enum { PS_OPT_SHARE_THIRD_CENTRE = 1 };
+int32_t ps_set_option(ps_ctx* ctx, int32_t option, int64_t value);
+
 /* Measured matrix-pipe throughput of the context's device, for reading roofline fractions against
  * what the chip sustains: a probe kernel in which every wave (16 per compute unit) issues long runs of
  * independent 16x16x4 MFMAs (FP64 for PS_PREC_FP64, FP32 for PS_PREC_MIXED) on register operands;

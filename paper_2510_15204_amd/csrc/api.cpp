@@ -15,6 +15,8 @@
 
 namespace psint {
 
+hipError_t launch_eval_shared(bool fp32, const ShareSegDev* segs, int nseg, int64_t nblocks, const GridDev* grids,
+                              const double* lines, const ShellDev* shells, const MEntry* ments, hipStream_t st);
 hipError_t launch_eval(bool fp32, const SegDev* segs, int nseg, int64_t nblocks, const GridDev* grids,
                        const double* lines, const ShellDev* shells, const MEntry* ments, const WColDev* wcols,
                        hipStream_t st);
@@ -185,6 +187,10 @@ void compute_layout(const Plan& p, Layout& L) {
   L.ments = take(p.ments.size() * sizeof(MEntry));
   L.wcols = take(p.wcols.size() * sizeof(WColDev));
   L.segs = take(p.segs.size() * sizeof(SegDev));
+  L.ssegs = take(p.ssegs.size() * sizeof(ShareSegDev));
+  size_t nmem = 0;
+  for (int h : p.ssegs) nmem += p.shares[h].grids.size();
+  L.smembers = take(nmem * sizeof(ShareMember));
   L.tasks = take(p.tasks.size() * sizeof(TaskDev));
   L.tiles = take(p.tiles.size() * sizeof(TileDev));
   L.reds = take(p.reds.size() * sizeof(RedDev));
@@ -220,6 +226,28 @@ static void stage_meta(const Plan& p, const Layout& L, char* base, char* host) {
     segs[i].arr1d = at(p.segs[i].arr1d);
   }
   put(L.segs, segs.data(), segs.size() * sizeof(SegDev));
+  {
+    std::vector<ShareSegDev> ss;
+    std::vector<ShareMember> mem;
+    auto at = [&](int a) -> void* { return a >= 0 ? base + L.arrays + p.arrays[a].offset : nullptr; };
+    for (int h : p.ssegs) {
+      const ShareHost& sh = p.shares[h];
+      ShareSegDev d = sh.dev;
+      d.members = (const ShareMember*)(base + L.smembers) + mem.size();
+      d.cells = (const int32_t*)(base + L.ints) + sh.cells_off;
+      for (size_t c = 0; c < sh.grids.size(); ++c) {
+        ShareMember m;
+        m.arr0 = at(sh.arr0[c]);
+        m.arr0d = at(sh.arr0d[c]);
+        m.grid = sh.grids[c];
+        m.pad0 = 0;
+        mem.push_back(m);
+      }
+      ss.push_back(d);
+    }
+    put(L.ssegs, ss.data(), ss.size() * sizeof(ShareSegDev));
+    put(L.smembers, mem.data(), mem.size() * sizeof(ShareMember));
+  }
   const int32_t* ints_dev = (const int32_t*)(base + L.ints);
   double* out_dev = (double*)(base + L.out);
   std::vector<TaskDev> tasks(p.tasks.size());
@@ -268,9 +296,13 @@ int32_t enqueue_segment(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, in
   const int32_t* items = (const int32_t*)(base + L.items);
   const bool mixed = p.precision == PS_PREC_MIXED;
   auto eval = [&](const Pass& ps) {
-    return launch_eval(mixed, segs + ps.seg0, ps.seg1 - ps.seg0, ps.eval_blocks, grids, lines,
-                       (const ShellDev*)(base + L.shells), (const MEntry*)(base + L.ments),
-                       (const WColDev*)(base + L.wcols), st);
+    hipError_t e = launch_eval(mixed, segs + ps.seg0, ps.seg1 - ps.seg0, ps.eval_blocks, grids, lines,
+                               (const ShellDev*)(base + L.shells), (const MEntry*)(base + L.ments),
+                               (const WColDev*)(base + L.wcols), st);
+    if (e != hipSuccess) return e;
+    return launch_eval_shared(mixed, (const ShareSegDev*)(base + L.ssegs) + ps.sseg0, ps.sseg1 - ps.sseg0,
+                              ps.shared_blocks, grids, lines, (const ShellDev*)(base + L.shells),
+                              (const MEntry*)(base + L.ments), st);
   };
   if (k == 0) {
     HIP_TRY(hipMemcpyAsync(base, s.pinned, L.meta_end, hipMemcpyHostToDevice, st));
@@ -430,9 +462,16 @@ TileShape effective_shape(const ps_ctx* ctx, int32_t precision) {
   return t;
 }
 
+// Cross-third-centre reuse for a job: the context's choice, or automatically for FP64 jobs (measured
+// on the hydrocarbon job: FP64 0.3% faster with it, mixed 0.2% slower).
+bool share_third_for(const ps_ctx* ctx, int32_t precision) {
+  return ctx->share_third < 0 ? precision == PS_PREC_FP64 : ctx->share_third != 0;
+}
+
 int32_t plan_job(ps_ctx* ctx, const ps_job* job, Plan& plan, Layout& L) {
   std::string err;
-  int32_t rc = build_plan(job, effective_shape(ctx, job->precision), ctx->ksplit, ctx->budget, &plan, &err);
+  int32_t rc = build_plan(job, effective_shape(ctx, job->precision), ctx->ksplit, ctx->budget, &plan, &err,
+                          share_third_for(ctx, job->precision));
   if (rc) {
     set_err(ctx, err);
     return rc;
@@ -641,6 +680,16 @@ int32_t ps_mfma_rate(ps_ctx* ctx, int32_t precision, double* tflops) {
   return rc;
 }
 
+int32_t ps_set_option(ps_ctx* ctx, int32_t option, int64_t value) {
+  if (!ctx) return PS_E_INVALID;
+  if (option == PS_OPT_SHARE_THIRD_CENTRE && (value == -1 || value == 0 || value == 1)) {
+    ctx->share_third = (int)value;
+    return PS_OK;
+  }
+  set_err(ctx, "option: PS_OPT_SHARE_THIRD_CENTRE with value -1, 0 or 1");
+  return PS_E_INVALID;
+}
+
 int32_t ps_set_tiling(ps_ctx* ctx, int32_t wm, int32_t wn, int32_t stage_chunks, int32_t ksplit) {
   if (!ctx) return PS_E_INVALID;
   if (wm == 0 && wn == 0 && stage_chunks == 0) {
@@ -690,8 +739,9 @@ static std::vector<char> plan_inputs(const ps_ctx* ctx, const ps_job* job) {
   const int tv[4] = {t.wm, t.wn, t.sc, ctx->ksplit};
   put(tv, sizeof tv);
   put(&ctx->budget, sizeof ctx->budget);
-  const char chol = job->PQ_chol != nullptr;
+  const char chol = job->PQ_chol != nullptr, share = share_third_for(ctx, job->precision);
   put(&chol, 1);
+  put(&share, 1);
   return v;
 }
 

@@ -21,7 +21,7 @@ namespace psint {
 
 // Device layout of one planned job: tables, then arrays, workspace and the FP64 output buffer.
 struct Layout {
-  size_t grids, lines, shells, ments, wcols, segs, tasks, tiles, reds, ints, items, status;
+  size_t grids, lines, shells, ments, wcols, segs, ssegs, smembers, tasks, tiles, reds, ints, items, status;
   size_t meta_end;
   size_t arrays, ws, out;
   size_t total;
@@ -78,6 +78,7 @@ struct ps_ctx {
   psint::TileShape shape;
   bool shape_explicit = false;  // false: the default shape of the job's precision
   int ksplit = 0;
+  int share_third = -1;  // PS_OPT_SHARE_THIRD_CENTRE: -1 automatic (FP64 jobs), 0 off, 1 on
   psint::Slot sync_slot;
   std::mutex sync_mu;  // held while ps_compute / ps_autotune use sync_slot; the serving dispatcher
                        // takes an idle sync_slot's arena back when a queued job needs the memory

@@ -10,6 +10,8 @@ namespace psint {
 void compute_layout(const Plan& p, Layout& L);
 // The contraction tile shape for a job: the context's explicit choice, else the precision's default.
 TileShape effective_shape(const ps_ctx* ctx, int32_t precision);
+// Whether a job of this precision on this context uses cross-third-centre reuse.
+bool share_third_for(const ps_ctx* ctx, int32_t precision);
 // Plan the job and size its device layout (PS_E_NOMEM beyond the budget).
 int32_t plan_job(ps_ctx* ctx, const ps_job* job, Plan& plan, Layout& L);
 // Size the slot's arena and pinned staging (plus `extra_pinned` bytes) and stage the tables.

@@ -183,6 +183,40 @@ __device__ __forceinline__ void inc_gamma_pair(int k_lo, int k_up, double x, dou
 }
 
 // ------------------------------------------------------------------------------------------------
+// Real solid harmonics of the unit displacement (x, y, z) at degree l from degrees l - 1 (Cm1, Sm1)
+// and l - 2 (Cm2, Sm2) into C, Sv (the recurrences below).
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ void harmonic_level(int l, double x, double y, double z, const double* Cm2,
+                                               const double* Sm2, const double* Cm1, const double* Sm1,
+                                               double* C, double* Sv) {
+  if (l == 0) {
+    C[0] = 1.0;
+    Sv[0] = 0.0;
+    return;
+  }
+  const double tl = 2.0 * l - 1.0;
+#pragma unroll
+  for (int m = 0; m <= LMAX; ++m) {
+    double cn = 0.0, sn = 0.0;
+    if (m == l) {
+      if (m >= 1) {
+        cn = tl * (x * Cm1[m >= 1 ? m - 1 : 0] - y * Sm1[m >= 1 ? m - 1 : 0]);
+        sn = tl * (y * Cm1[m >= 1 ? m - 1 : 0] + x * Sm1[m >= 1 ? m - 1 : 0]);
+      }
+    } else if (m == l - 1) {
+      cn = tl * z * Cm1[m];
+      sn = tl * z * Sm1[m];
+    } else if (m < l - 1) {
+      const double inv = kInv.v[l - m];
+      cn = (tl * z * Cm1[m] - (l + m - 1.0) * Cm2[m]) * inv;
+      sn = (tl * z * Sm1[m] - (l + m - 1.0) * Sm2[m]) * inv;
+    }
+    C[m] = cn;
+    Sv[m] = sn;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
 // Evaluation kernel.  Real solid harmonics of the unit displacement by the Cartesian recurrences
 //   C_l^l = (2l-1)(x C_{l-1}^{l-1} - y S_{l-1}^{l-1}),  S_l^l = (2l-1)(y C_{l-1}^{l-1} + x S_{l-1}^{l-1}),
 //   C_l^{l-1} = (2l-1) z C_{l-1}^{l-1},  (l-m) C_l^m = (2l-1) z C_{l-1}^m - (l+m-1) C_{l-2}^m,
@@ -248,6 +282,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void e
     }
     return;
   }
+  if (S.skip) {
+    // cells a shared segment writes (Q = 4: a wave's 64 points are one cell, so whole waves leave)
+    const int64_t c = g >> 6;
+    if (c < G.n_reg) {
+      const int64_t plane = (int64_t)G.nnu * G.nphi;
+      const int i = (int)(c / plane), j = (int)((c - (int64_t)i * plane) / G.nphi);
+      if (((S.skip_mu[i >> 6] >> (i & 63)) & 1) && ((S.skip_nu[j >> 6] >> (j & 63)) & 1)) return;
+    }
+  }
   Geo geo;
   point_geo(G, lines, g, geo);
   if (S.mode == EV_WEIGHTS) {
@@ -280,31 +323,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void e
   for (int l = 0; l <= LMAX; ++l)
     if (S.l_off[l + 1] > S.l_off[l]) lmax_seg = l;
   for (int l = 0; l <= lmax_seg; ++l) {
-    if (l == 0) {
-      C[0] = 1.0;
-      Sv[0] = 0.0;
-    } else {
-      const double tl = 2.0 * l - 1.0;
-#pragma unroll
-      for (int m = 0; m <= LMAX; ++m) {
-        double cn = 0.0, sn = 0.0;
-        if (m == l) {
-          if (m >= 1) {
-            cn = tl * (x * Cm1[m >= 1 ? m - 1 : 0] - y * Sm1[m >= 1 ? m - 1 : 0]);
-            sn = tl * (y * Cm1[m >= 1 ? m - 1 : 0] + x * Sm1[m >= 1 ? m - 1 : 0]);
-          }
-        } else if (m == l - 1) {
-          cn = tl * z * Cm1[m];
-          sn = tl * z * Sm1[m];
-        } else if (m < l - 1) {
-          const double inv = kInv.v[l - m];
-          cn = (tl * z * Cm1[m] - (l + m - 1.0) * Cm2[m]) * inv;
-          sn = (tl * z * Sm1[m] - (l + m - 1.0) * Sm2[m]) * inv;
-        }
-        C[m] = cn;
-        Sv[m] = sn;
-      }
-    }
+    harmonic_level(l, x, y, z, Cm2, Sm2, Cm1, Sm1, C, Sv);
     // shells with this l
     for (int s = S.l_off[l]; s < S.l_off[l + 1]; ++s) {
       const ShellDev sh = shells[s];
@@ -356,6 +375,133 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void e
       Sm2[m] = Sm1[m];
       Cm1[m] = C[m];
       Sm1[m] = Sv[m];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Shared evaluation (ShareSegDev): one wave per shared cell (Q = 4), one thread per point.  The
+// local coordinates and the distance to the segment's centre follow point_geo for a regular cell;
+// the displacement in each member's frame is that grid's own (lx ex + ly ey + lz ez).  Per shell the
+// radial factor is computed once for all members; the harmonics of each degree are rebuilt per member
+// from degree 0 (a few multiply-adds against the exp and power the members share).
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void eval_shared_kernel(const ShareSegDev* __restrict__ segs, int nseg,
+                                                          const GridDev* __restrict__ grids,
+                                                          const double* __restrict__ lines,
+                                                          const ShellDev* __restrict__ shells,
+                                                          const MEntry* __restrict__ ments) {
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].block0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const ShareSegDev& S = segs[lo];
+  const ShareMember* __restrict__ mem = S.members;
+  const GridDev& G0 = grids[mem[0].grid];
+  const int lane = threadIdx.x & 63;
+  const int64_t wv = (b - S.block0) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t ncell = (int64_t)S.n_si * S.n_sj * G0.nphi;
+  if (wv >= ncell) return;
+  const int k = (int)(wv % G0.nphi);
+  const int64_t t2 = wv / G0.nphi;
+  const int i = S.cells[t2 / S.n_sj], j = S.cells[S.n_si + (int)(t2 % S.n_sj)];
+  const int64_t gw = (((int64_t)i * G0.nnu + j) * G0.nphi + k) * 64;  // the cell's first point
+  // point (p, q, r) = lane of the cell, as point_geo maps a regular cell (no split)
+  const int ip = lane >> 4, iq = (lane >> 2) & 3, ir = lane & 3;
+  const double* mu = lines + G0.lines;
+  const double* nu = mu + G0.nmu + 1;
+  const double* ph = nu + G0.nnu + 1;
+  const double* glx = lines + G0.gl;
+  const double inv = 1.0;
+  const double hm = (mu[i + 1] - mu[i]) * inv, hn = (nu[j + 1] - nu[j]) * inv, hp = (ph[k + 1] - ph[k]) * inv;
+  const double m = mu[i] + hm * (0 + 0.5 * (1.0 + glx[ip]));
+  const double n = nu[j] + hn * (0 + 0.5 * (1.0 + glx[iq]));
+  const double f = ph[k] + hp * (0 + 0.5 * (1.0 + glx[ir]));
+  const double shh = sinh(0.5 * m);
+  const double s2 = shh * shh;
+  const double chh = sqrt(1.0 + s2);
+  double sn2, cs2, sf, cf;
+  sincos(0.5 * n, &sn2, &cs2);
+  sincos(f, &sf, &cf);
+  const double sh = 2.0 * shh * chh;
+  const double sn = 2.0 * sn2 * cs2, cs = (cs2 - sn2) * (cs2 + sn2);
+  const double a = G0.a;
+  const double rho = a * sh * sn;
+  const double lx = rho * cf, ly = rho * sf;
+  const bool onA = S.centre == CEN_A;
+  const double lz = onA ? a * (2.0 * s2 * cs - 2.0 * sn2 * sn2) : a * (2.0 * s2 * cs + 2.0 * cs2 * cs2);
+  const double r = onA ? 2.0 * a * (s2 + sn2 * sn2) : 2.0 * a * (s2 + cs2 * cs2);
+  const double ir_ = 1.0 / r;
+  typedef __attribute__((address_space(1))) T GT;
+  typedef __attribute__((address_space(1))) double GD;
+  const uint32_t loff = (uint32_t)((lane >> 4) * S.nf * KC + (lane & 15));
+  int lmax_seg = 0;
+  for (int l = 0; l <= LMAX; ++l)
+    if (S.l_off[l + 1] > S.l_off[l]) lmax_seg = l;
+  constexpr int GROUP = 8;  // shells of one degree whose radial factors are held at once
+  for (int l = 0; l <= lmax_seg; ++l) {
+    for (int s0 = S.l_off[l]; s0 < S.l_off[l + 1]; s0 += GROUP) {
+      const int ns = min(GROUP, S.l_off[l + 1] - s0);
+      double rad[GROUP];
+#pragma unroll
+      for (int u = 0; u < GROUP; ++u) {
+        rad[u] = 0.0;
+        if (u < ns) {
+          const ShellDev shl = shells[s0 + u];
+          const double ex = exp(-shl.zeta * r);
+          rad[u] = shl.norm * ipow(r, shl.n - 1) * ex;
+        }
+      }
+      for (int c = 0; c < S.n_members; ++c) {
+        const GridDev& G = grids[mem[c].grid];
+        const double dx = lx * G.ex[0] + ly * G.ey[0] + lz * G.ez[0];
+        const double dy = lx * G.ex[1] + ly * G.ey[1] + lz * G.ez[1];
+        const double dz = lx * G.ex[2] + ly * G.ey[2] + lz * G.ez[2];
+        const double x = dx * ir_, y = dy * ir_, z = dz * ir_;
+        double Cm2[LMAX + 1], Sm2[LMAX + 1], Cm1[LMAX + 1], Sm1[LMAX + 1], C[LMAX + 1], Sv[LMAX + 1];
+#pragma unroll
+        for (int mm = 0; mm <= LMAX; ++mm) Cm2[mm] = Sm2[mm] = Cm1[mm] = Sm1[mm] = C[mm] = Sv[mm] = 0.0;
+        for (int ll = 0; ll <= l; ++ll) {
+          harmonic_level(ll, x, y, z, Cm2, Sm2, Cm1, Sm1, C, Sv);
+          if (ll < l) {
+#pragma unroll
+            for (int mm = 0; mm <= LMAX; ++mm) {
+              Cm2[mm] = Cm1[mm];
+              Sm2[mm] = Sm1[mm];
+              Cm1[mm] = C[mm];
+              Sm1[mm] = Sv[mm];
+            }
+          }
+        }
+        GT* __restrict__ w0 = (GT*)mem[c].arr0 + gw * S.nf;
+        GD* __restrict__ d0 = (GD*)mem[c].arr0d + gw * S.nf;
+        const bool has0 = mem[c].arr0 != nullptr, has0d = sizeof(T) == 4 && mem[c].arr0d != nullptr;
+#pragma unroll
+        for (int u = 0; u < GROUP; ++u) {
+          if (u >= ns) break;
+          const ShellDev shl = shells[s0 + u];
+          const MEntry* __restrict__ me0 = ments + shl.m_off + l;
+#pragma unroll
+          for (int mm = 0; mm <= LMAX; ++mm) {
+            if (mm > l) break;
+            const MEntry ep = me0[mm], en = me0[-mm];
+            if (ep.col >= 0) {
+              const double v = rad[u] * (C[mm] * ep.f);
+              if (has0) w0[(int64_t)ep.col * KC + loff] = (T)v;
+              if (has0d) d0[(int64_t)ep.col * KC + loff] = v;
+            }
+            if (mm > 0 && en.col >= 0) {
+              const double v = rad[u] * (Sv[mm] * en.f);
+              if (has0) w0[(int64_t)en.col * KC + loff] = (T)v;
+              if (has0d) d0[(int64_t)en.col * KC + loff] = v;
+            }
+          }
+        }
+      }
     }
   }
 }
@@ -1027,6 +1173,18 @@ hipError_t launch_eval(bool fp32, const SegDev* segs, int nseg, int64_t nblocks,
   else
     hipLaunchKernelGGL(eval_kernel<double>, dim3((unsigned)nblocks), dim3(256), 0, st, segs, nseg, grids, lines,
                        shells, ments, wcols);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_shared(bool fp32, const ShareSegDev* segs, int nseg, int64_t nblocks, const GridDev* grids,
+                              const double* lines, const ShellDev* shells, const MEntry* ments, hipStream_t st) {
+  if (nblocks <= 0 || nseg <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(eval_shared_kernel<float>, dim3((unsigned)nblocks), dim3(256), 0, st, segs, nseg, grids, lines,
+                       shells, ments);
+  else
+    hipLaunchKernelGGL(eval_shared_kernel<double>, dim3((unsigned)nblocks), dim3(256), 0, st, segs, nseg, grids,
+                       lines, shells, ments);
   return hipGetLastError();
 }
 

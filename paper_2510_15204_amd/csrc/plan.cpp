@@ -372,7 +372,7 @@ static void xcd_order(std::vector<TileDev>& tiles, int t0, int t1) {
 }
 
 int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_override, size_t budget,
-                   Plan* P, std::string* err) {
+                   Plan* P, std::string* err, bool share_third) {
   int32_t rc = validate_job(job, err);
   if (rc) return rc;
   Plan& p = *P;
@@ -870,6 +870,82 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
     }
   }
 
+  // ---- cross-third-centre reuse (optional) ----
+  // The grids G(A,B|C) of one pair other than its pair grid differ only by a rotation about the A-B
+  // axis (each puts its own C at phi = 0) and by the lines moved onto their C.  In the regular cells
+  // no member's moved lines touch, their points share (mu, nu, phi) and the distances to A and B:
+  // one shared segment per atom evaluates those cells for all members (radial factors once), and
+  // the members' own basis segments skip them.  Needs Q = 4 (a cell is one wave) and at most 128
+  // cells per axis (the skip masks).
+  if (share_third && N >= 4) {
+    std::map<std::pair<int, int>, std::vector<int>> members_of;
+    for (int gi = 0; gi < (int)p.grids.size(); ++gi)
+      if (!p.grids[gi].pair_grid && p.grids[gi].C >= 0) members_of[{p.grids[gi].A, p.grids[gi].B}].push_back(gi);
+    for (auto& kv : members_of) {
+      const std::vector<int>& mg = kv.second;
+      if (mg.size() < 2) continue;
+      const GridDev& g0 = p.grids[mg[0]].dev;
+      if (g0.q != 4 || g0.nmu > 128 || g0.nnu > 128) continue;
+      std::vector<char> mu_ok(g0.nmu, 1), nu_ok(g0.nnu, 1);
+      for (int gi : mg) {
+        const GridDev& d = p.grids[gi].dev;
+        if (d.istar > 0) mu_ok[d.istar - 1] = mu_ok[d.istar] = 0;  // cells on either side of a moved line
+        if (d.jstar > 0) nu_ok[d.jstar - 1] = nu_ok[d.jstar] = 0;
+      }
+      std::vector<int32_t> cells;
+      uint64_t mmask[2] = {0, 0}, nmask[2] = {0, 0};
+      for (int i = 0; i < g0.nmu; ++i)
+        if (mu_ok[i]) {
+          cells.push_back(i);
+          mmask[i >> 6] |= 1ull << (i & 63);
+        }
+      const int n_si = (int)cells.size();
+      for (int j = 0; j < g0.nnu; ++j)
+        if (nu_ok[j]) {
+          cells.push_back(j);
+          nmask[j >> 6] |= 1ull << (j & 63);
+        }
+      const int n_sj = (int)cells.size() - n_si;
+      if (n_si == 0 || n_sj == 0) continue;
+      const int64_t cells_off = push_ints(cells);
+      for (int side = 0; side < 2; ++side) {
+        const int centre = side == 0 ? CEN_A : CEN_B;
+        ShareHost sh;
+        for (int gi : mg)
+          for (int si = 0; si < (int)p.segs.size(); ++si) {
+            const SegHost& sg = p.segs[si];
+            if (sg.dev.grid == gi && sg.dev.mode == EV_CHI && sg.dev.centre == centre) {
+              sh.grids.push_back(gi);
+              sh.segs.push_back(si);
+              sh.arr0.push_back(sg.arr0);
+              sh.arr0d.push_back(sg.arr0d);
+            }
+          }
+        if (sh.segs.size() != mg.size()) continue;
+        const SegDev& d0 = p.segs[sh.segs[0]].dev;
+        std::memset(&sh.dev, 0, sizeof sh.dev);
+        sh.dev.centre = centre;
+        sh.dev.nf = d0.nf;
+        sh.dev.n_members = (int)mg.size();
+        sh.dev.n_si = n_si;
+        sh.dev.n_sj = n_sj;
+        sh.dev.item_off = d0.item_off;  // every member lists the same shells
+        sh.dev.n_items = d0.n_items;
+        for (int l = 0; l <= LMAX + 1; ++l) sh.dev.l_off[l] = d0.l_off[l];
+        sh.cells_off = cells_off;
+        for (int si : sh.segs) {
+          SegDev& d = p.segs[si].dev;
+          d.skip = 1;
+          d.skip_mu[0] = mmask[0];
+          d.skip_mu[1] = mmask[1];
+          d.skip_nu[0] = nmask[0];
+          d.skip_nu[1] = nmask[1];
+        }
+        p.shares.push_back(sh);
+      }
+    }
+  }
+
   // ---- passes: group grids so that arrays + workspace fit the budget ----
   const TileShape& shape2 = p.tile2;
   // row tiles of a task: BM consecutive pairs, halved until their staged U + V columns fit
@@ -972,6 +1048,36 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       off = (off + 255) / 256 * 256;
     }
     ps.array_bytes = off;
+  }
+  // shared segments: kept only when all members are in one pass; block offsets per pass
+  {
+    std::vector<int> pass_of(p.grids.size(), -1);
+    for (int k = 0; k < (int)p.passes.size(); ++k)
+      for (int gi = p.passes[k].grid0; gi < p.passes[k].grid1; ++gi) pass_of[gi] = k;
+    for (auto& sh : p.shares)
+      for (int gi : sh.grids)
+        if (pass_of[gi] != pass_of[sh.grids[0]]) sh.dropped = true;
+    for (auto& sh : p.shares)
+      if (sh.dropped)
+        for (int si : sh.segs) {
+          SegDev& d = p.segs[si].dev;
+          d.skip = 0;
+          d.skip_mu[0] = d.skip_mu[1] = d.skip_nu[0] = d.skip_nu[1] = 0;
+        }
+    for (int k = 0; k < (int)p.passes.size(); ++k) {
+      Pass& ps = p.passes[k];
+      ps.sseg0 = (int)p.ssegs.size();
+      int64_t blk = 0;
+      for (int h = 0; h < (int)p.shares.size(); ++h) {
+        ShareHost& sh = p.shares[h];
+        if (sh.dropped || pass_of[sh.grids[0]] != k) continue;
+        sh.dev.block0 = blk;
+        blk += ((int64_t)sh.dev.n_si * sh.dev.n_sj * p.grids[sh.grids[0]].dev.nphi + 3) / 4;
+        p.ssegs.push_back(h);
+      }
+      ps.sseg1 = (int)p.ssegs.size();
+      ps.shared_blocks = blk;
+    }
   }
   // segments: block offsets per pass
   {

@@ -52,6 +52,15 @@ struct SegHost {
   int arr0d = -1, arr1d = -1;  // FP64 copies written beside FP32 arr0 / arr1 (mixed jobs)
 };
 
+// A shared evaluation (cross-third-centre reuse): the device segment, its members' array ids and
+// the members' own basis segments (which skip the shared cells).
+struct ShareHost {
+  ShareSegDev dev;
+  std::vector<int> grids, arr0, arr0d, segs;
+  int64_t cells_off = 0;    // int offset of the shared mu and nu cell lists
+  bool dropped = false;     // members in different memory passes: no sharing
+};
+
 struct TaskHost {
   TaskDev dev;
   int grid;
@@ -68,6 +77,8 @@ struct Pass {
   int seg0, seg1;       // segments
   int task0, task1;     // tasks
   int tile0, tile1;     // all tiles of the pass
+  int sseg0 = 0, sseg1 = 0;     // shared evaluation segments (Plan::ssegs)
+  int64_t shared_blocks = 0;    // blocks of their launch
   struct Launch {
     int tile0, tile1;   // consecutive tiles of one contraction launch
     TileShape shape;
@@ -99,6 +110,8 @@ struct Plan {
   std::vector<MEntry> ments;
   std::vector<WColDev> wcols;
   std::vector<SegHost> segs;
+  std::vector<ShareHost> shares;     // all candidate shared segments (some dropped)
+  std::vector<int> ssegs;            // kept shares, in pass order (indices into shares)
   std::vector<TaskHost> tasks;
   std::vector<TileDev> tiles;
   std::vector<RedDev> reds;
@@ -122,7 +135,7 @@ int32_t validate_job(const ps_job* job, std::string* err);
 
 // Build the full plan.  `budget` bounds array + workspace bytes per pass.
 int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_override, size_t budget,
-                   Plan* plan, std::string* err);
+                   Plan* plan, std::string* err, bool share_third = false);
 
 // Grid construction alone (used by the inspection hook).
 int32_t build_grid(const ps_atom* atoms, int n_atoms, int A, int B, int C, const ps_grid_spec& spec,

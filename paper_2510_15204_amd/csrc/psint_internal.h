@@ -76,6 +76,36 @@ struct SegDev {
   int32_t item_off;   // shells or weight columns
   int32_t n_items;
   int32_t l_off[LMAX + 2];  // shells of angular momentum l are items [l_off[l], l_off[l+1])
+  // Regular cells (i, j, any k) whose bits are set in both masks are written by a shared segment
+  // (ShareSegDev) instead; only basis segments of grids with Q = 4 and at most 128 cells per axis.
+  int32_t skip;
+  int32_t pad1;
+  uint64_t skip_mu[2], skip_nu[2];
+};
+
+// One grid of a shared evaluation: its output array for the shared atom's basis values (FP32 or FP64
+// per precision; NULL: none) and FP64 twin (mixed jobs; NULL: none).
+struct ShareMember {
+  void* arr0;
+  void* arr0d;
+  int32_t grid;
+  int32_t pad0;
+};
+
+// Basis values of one atom (centre A or B) at corresponding points of several grids G(A,B|C) of one
+// pair.  Those grids differ only by a rotation about the A-B axis and by their moved lines, so in
+// the regular cells that no member's moved lines touch, their points share (mu, nu, phi), the
+// distances to A and B and hence every radial factor; each wave takes one such cell (Q = 4: 64
+// points), computes the radial factors once and the angular factors in each member's frame.
+struct ShareSegDev {
+  const ShareMember* members;
+  const int32_t* cells;     // shared mu cell indices [n_si], then shared nu cell indices [n_sj]
+  int64_t block0;           // first block of this segment in the shared-evaluation launch
+  int32_t centre;           // CEN_A / CEN_B
+  int32_t nf;               // columns of each member's array
+  int32_t n_members, n_si, n_sj;
+  int32_t item_off, n_items;
+  int32_t l_off[LMAX + 2];
 };
 
 // One contraction C[(u,v)][y] = sum_g U[u][g] V[v][g] Y[y][g] over one grid.  The result for pair

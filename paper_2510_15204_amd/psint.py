@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpsint.so")
 PS_OK, PS_E_INVALID, PS_E_UNSUPPORTED, PS_E_NOMEM, PS_E_DEVICE, PS_E_NOT_PD, PS_E_TIMEOUT, \
     PS_E_QUEUE_FULL, PS_E_NOT_FOUND = 0, -1, -2, -3, -4, -5, -6, -7, -8
 PREC = {"fp64": 0, "mixed": 1}
+PS_OPT_SHARE_THIRD_CENTRE = 1
 OUTPUTS = ("S", "T", "V", "PQ", "PQ_chol", "abP")
 
 
@@ -111,13 +112,14 @@ def lib():
         L.ps_ri_assemble.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp, _dp]
         L.ps_mfma_rate.argtypes = [vp, C.c_int32, _dp]
         L.ps_ri_assemble_noalloc.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, vp]
+        L.ps_set_option.argtypes = [vp, C.c_int32, C.c_int64]
         L.ps_status_string.argtypes = [C.c_int32]
         L.ps_status_string.restype = C.c_char_p
         L.ps_last_error.argtypes = [vp]
         L.ps_last_error.restype = C.c_char_p
         for f in ("ps_create", "ps_destroy", "ps_compute", "ps_submit", "ps_wait", "ps_grid_points",
                   "ps_eval_function", "ps_plan_work", "ps_set_tiling", "ps_autotune", "ps_ri_assemble",
-                  "ps_mfma_rate", "ps_ri_assemble_noalloc"):
+                  "ps_mfma_rate", "ps_ri_assemble_noalloc", "ps_set_option"):
             getattr(L, f).restype = C.c_int32
         _LIB = L
     return _LIB
@@ -138,7 +140,7 @@ def plan_work_host(job, precision=None):
 def exported_symbols():
     return ["ps_create", "ps_destroy", "ps_compute", "ps_submit", "ps_wait", "ps_grid_points",
             "ps_eval_function", "ps_plan_work", "ps_set_tiling", "ps_autotune", "ps_ri_assemble",
-            "ps_mfma_rate", "ps_ri_assemble_noalloc", "ps_status_string", "ps_last_error"]
+            "ps_mfma_rate", "ps_ri_assemble_noalloc", "ps_set_option", "ps_status_string", "ps_last_error"]
 
 
 def _spec(s) -> GridSpec:
@@ -224,6 +226,9 @@ class Context:
             msg = lib().ps_last_error(self.h)
             raise PsError(rc, (msg or b"").decode() or lib().ps_status_string(rc).decode())
         return rc
+
+    def set_option(self, option, value):
+        self._check(lib().ps_set_option(self.h, int(option), int(value)))
 
     def set_tiling(self, wm=0, wn=0, stage_chunks=0, ksplit=0):
         self._check(lib().ps_set_tiling(self.h, wm, wn, stage_chunks, ksplit))

@@ -71,7 +71,8 @@ int main(int argc, char** argv) {
   const size_t budget = (size_t)(atof(argv[4]) * 1e9);
   Plan p;
   std::string err;
-  if (build_plan(&job, ts, 0, budget, &p, &err) != PS_OK) {
+  const bool share = argc > 5 && std::string(argv[5]) == "share";
+  if (build_plan(&job, ts, 0, budget, &p, &err, share) != PS_OK) {
     printf("FAIL plan %s\n", err.c_str());
     return 1;
   }
@@ -144,6 +145,48 @@ int main(int argc, char** argv) {
     for (size_t e = 0; e < cover[t].size(); ++e)
       if (cover[t][e] != 1) return fail("element of no item", (long)t, (long)e);
   if (issued != p.issued_flops) return fail("issued FLOPs", (long)(issued / 1e9), (long)(p.issued_flops / 1e9));
-  printf("ok %zu tiles %zu items %zu passes\n", p.tiles.size(), p.reds.size(), p.passes.size());
+
+  // shared evaluation (cross-third-centre reuse): kept shares have all members in one pass and are
+  // listed in that pass; their cells avoid every member's moved lines; each member's basis segment
+  // skips exactly those cells; dropped shares leave no skipping segment; the launch covers the cells
+  size_t kept = 0;
+  std::vector<int> skipped_by(p.segs.size(), 0);
+  for (int k = 0; k < (int)p.passes.size(); ++k) {
+    const Pass& ps = p.passes[k];
+    int64_t blk = 0;
+    for (int x = ps.sseg0; x < ps.sseg1; ++x) {
+      const ShareHost& sh = p.shares[p.ssegs[x]];
+      ++kept;
+      if (sh.dropped) return fail("dropped share listed", x);
+      if (sh.dev.block0 != blk) return fail("share block offset", x);
+      const GridDev& g0 = p.grids[sh.grids[0]].dev;
+      blk += ((int64_t)sh.dev.n_si * sh.dev.n_sj * g0.nphi + 3) / 4;
+      const int32_t* cells = p.ints.data() + sh.cells_off;
+      for (size_t c = 0; c < sh.grids.size(); ++c) {
+        const int gi = sh.grids[c];
+        if (gi < ps.grid0 || gi >= ps.grid1) return fail("share member outside its pass", x, gi);
+        const GridDev& d = p.grids[gi].dev;
+        if (d.q != 4 || d.nmu != g0.nmu || d.nnu != g0.nnu || d.nphi != g0.nphi) return fail("share member shape", x, gi);
+        const SegDev& sg = p.segs[sh.segs[c]].dev;
+        if (!sg.skip || sg.grid != gi || sg.centre != sh.dev.centre) return fail("member segment", x, gi);
+        skipped_by[sh.segs[c]]++;
+        uint64_t mm[2] = {0, 0}, nm[2] = {0, 0};
+        for (int t = 0; t < sh.dev.n_si; ++t) mm[cells[t] >> 6] |= 1ull << (cells[t] & 63);
+        for (int t = 0; t < sh.dev.n_sj; ++t) nm[cells[sh.dev.n_si + t] >> 6] |= 1ull << (cells[sh.dev.n_si + t] & 63);
+        if (mm[0] != sg.skip_mu[0] || mm[1] != sg.skip_mu[1] || nm[0] != sg.skip_nu[0] || nm[1] != sg.skip_nu[1])
+          return fail("skip masks differ from the shared cells", x, gi);
+        for (int t = 0; t < sh.dev.n_si; ++t)
+          if (d.istar > 0 && (cells[t] == d.istar - 1 || cells[t] == d.istar)) return fail("shared mu cell at a moved line", x, gi);
+        for (int t = 0; t < sh.dev.n_sj; ++t)
+          if (d.jstar > 0 && (cells[sh.dev.n_si + t] == d.jstar - 1 || cells[sh.dev.n_si + t] == d.jstar))
+            return fail("shared nu cell at a moved line", x, gi);
+      }
+    }
+    if (blk != ps.shared_blocks) return fail("shared blocks of a pass", k);
+  }
+  for (size_t si = 0; si < p.segs.size(); ++si)
+    if ((p.segs[si].dev.skip != 0) != (skipped_by[si] == 1)) return fail("segment skips without one share", (long)si);
+  if (share && kept == 0) return fail("no share kept");
+  printf("ok %zu tiles %zu items %zu passes %zu shares\n", p.tiles.size(), p.reds.size(), p.passes.size(), kept);
   return 0;
 }

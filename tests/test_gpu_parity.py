@@ -204,6 +204,61 @@ def test_repeated_not_positive_definite_job_factors_every_time():
     assert runs[2][1]["graph_replay"] == 1
 
 
+def _five_atoms():
+    """Five atoms off every pair axis (third centres refine every grid), Q = 4: each pair has two grids
+    G(A,B|C) besides its pair grid, so cross-third-centre reuse forms a shared segment per atom."""
+    xyz = np.array([[0.0, 0.0, 0.0], [2.1, 0.3, 0.2], [-0.6, 1.9, -0.4], [0.5, -0.9, 1.95], [1.6, 1.7, 1.5]])
+    basis, aux = [], []
+    for a in range(5):
+        basis += [[a, 1, 0, 0, 2.4 - 0.2 * a], [a, 2, 0, 0, 0.9], [a, 2, 1, -1, 1.3], [a, 2, 1, 0, 1.3],
+                  [a, 2, 1, 1, 1.3], [a, 3, 2, -2, 1.1], [a, 3, 2, 1, 1.1]]
+        aux += [[a, 1, 0, 0, 3.0], [a, 2, 1, 0, 2.2], [a, 3, 2, 2, 2.0]]
+    return MiniJob(xyz, [6.0, 1.0, 8.0, 1.0, 1.0], basis, aux, Spec(10, 10, 6, 4, 3))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_third_centre_reuse_matches_per_grid_evaluation_and_oracle(prec):
+    """Cross-third-centre reuse (ps_set_option PS_OPT_SHARE_THIRD_CENTRE): the shared evaluation does
+    the per-grid evaluation's arithmetic for the shared cells, so every output equals the job without
+    reuse to rounding (1e-13 of each type's largest element; FP32 values of the mixed job are rounded
+    from the same FP64 values), and the FP64 job equals the oracle to 1e-10."""
+    job = _five_atoms()
+    c = psint.Context(0)
+    try:
+        c.set_option(psint.PS_OPT_SHARE_THIRD_CENTRE, 0)
+        off, _, rc_off = c.compute(job, precision=prec)
+        c.set_option(psint.PS_OPT_SHARE_THIRD_CENTRE, 1)
+        on, _, rc_on = c.compute(job, precision=prec)
+        c.set_option(psint.PS_OPT_SHARE_THIRD_CENTRE, -1)  # automatic: on for FP64 jobs
+        auto, _, _ = c.compute(job, precision=prec)
+    finally:
+        c.close()
+    for k in psint.OUTPUTS:
+        assert np.array_equal(auto[k], on[k] if prec == "fp64" else off[k]), k
+    assert rc_on == rc_off
+    for k in ("S", "T", "V", "PQ", "abP"):
+        scale = max(1.0, float(np.max(np.abs(off[k]))))
+        d = float(np.max(np.abs(on[k] - off[k])))
+        _say(f"{prec} {k}: |shared - per grid| = {d:.2e}, identical {np.array_equal(on[k], off[k])}")
+        assert d <= 1e-13 * scale, (k, d)
+    if prec == "fp64":
+        ref = O.compute_full(job)
+        _compare(on, ref, TOL64, "five atoms, shared evaluation")
+
+
+def test_set_option_rejects_unknown():
+    c = psint.Context(0)
+    try:
+        with pytest.raises(psint.PsError) as e:
+            c.set_option(99, 1)
+        assert e.value.status == psint.PS_E_INVALID
+        with pytest.raises(psint.PsError):
+            c.set_option(psint.PS_OPT_SHARE_THIRD_CENTRE, 2)
+        c.set_option(psint.PS_OPT_SHARE_THIRD_CENTRE, -1)
+    finally:
+        c.close()
+
+
 @pytest.mark.parametrize("bad", ["l_ge_n", "neg_zeta", "atom_index", "coincident", "spec", "too_high_l"])
 def test_invalid_inputs_rejected(ctx, bad):
     xyz = np.array([[0.0, 0.0, 0.7], [0.0, 0.0, -0.7]])

@@ -2,7 +2,7 @@
 tests/plan_check.cpp) on the benchmark workloads and under a small memory budget: every output
 element of every task is covered by exactly one reduction item, each item's K splits tile its grid's
 point chunks in order and evenly, every tile sits in a launch whose shape holds it, and the issued
-FLOPs add up."""
+FLOPs add up; with cross-third-centre reuse, the shared segments and the cells their members skip."""
 import os
 import subprocess
 
@@ -35,19 +35,23 @@ def _write_job(job, path):
     path.write_text("\n".join(lines) + "\n")
 
 
-@pytest.mark.parametrize("name,prec,budget_gb", [
-    ("diatomic_small", 0, 200.0),
-    ("triatomic_qz", 0, 200.0),
-    ("triatomic_qz", 1, 200.0),
-    ("triatomic_qz", 0, 7.0),       # one grid per memory pass, small workspace reservations
-    ("hydrocarbon9", 0, 246.0),     # 252 uneven grids, three passes
-    ("hydrocarbon9", 1, 246.0),
+@pytest.mark.parametrize("name,prec,budget_gb,share", [
+    ("diatomic_small", 0, 200.0, ""),
+    ("triatomic_qz", 0, 200.0, ""),
+    ("triatomic_qz", 1, 200.0, ""),
+    ("triatomic_qz", 0, 7.0, ""),       # one grid per memory pass, small workspace reservations
+    ("hydrocarbon9", 0, 246.0, ""),     # 252 uneven grids, three passes
+    ("hydrocarbon9", 1, 246.0, ""),
+    ("hydrocarbon9", 0, 246.0, "share"),  # cross-third-centre reuse: shared segments, skip masks
+    ("hydrocarbon9", 1, 246.0, "share"),
+    ("hydrocarbon9", 0, 40.0, "share"),   # many passes: shares split by a pass boundary are dropped
 ])
-def test_plan_invariants(checker, name, prec, budget_gb):
+def test_plan_invariants(checker, name, prec, budget_gb, share):
     exe, d = checker
     job = getattr(W, name)()
     f = d / f"{name}.txt"
     _write_job(job, f)
-    out = subprocess.run([exe, str(f), str(prec), "512", str(budget_gb)], capture_output=True, text=True, timeout=300)
+    args = [exe, str(f), str(prec), "512", str(budget_gb)] + ([share] if share else [])
+    out = subprocess.run(args, capture_output=True, text=True, timeout=300)
     print(out.stdout.strip())
     assert out.returncode == 0 and out.stdout.startswith("ok"), out.stdout + out.stderr
