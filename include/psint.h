@@ -113,6 +113,7 @@ typedef struct {
   int64_t n_passes;      /* grid batches run one after another to fit the device-memory budget   */
   int64_t graph_replay;  /* 1: the device work ran as a replay of a captured HIP graph (ps_compute of
                             a job identical to the previous one on the context), else 0           */
+  int64_t passes_overlapped; /* 1: the passes ran overlapped (PS_OPT_OVERLAP_PASSES), else 0      */
 } ps_job_stats;
 
 typedef struct ps_ctx ps_ctx;
@@ -171,15 +172,27 @@ int32_t ps_plan_work(ps_ctx* ctx, const ps_job* job, double* pair_points, int64_
  * context when the job's inputs, the tiling and the budget are unchanged. */
 int32_t ps_set_tiling(ps_ctx* ctx, int32_t wm, int32_t wn, int32_t stage_chunks, int32_t ksplit);
 
-/* Context options for later jobs.  PS_OPT_SHARE_THIRD_CENTRE (value -1 = automatic, the default: on
- * for FP64 jobs, off for mixed ones; 0 = off; 1 = on): cross-third-centre reuse of basis values.  The grids G(A,B|C) of one atom pair, other than its pair
- * grid, differ only by a rotation about the A-B axis (each places its C at phi = 0, Section 2.3) and
- * by the lines moved onto their C (Section 2.2); in the regular cells that no such grid's moved lines
+/* Context options for later jobs; PS_E_INVALID for other options or values.
+ *
+ * PS_OPT_SHARE_THIRD_CENTRE (value -1 = automatic, the default: on for FP64 jobs, off for mixed ones;
+ * 0 = off; 1 = on): cross-third-centre reuse of basis values.  The grids G(A,B|C) of one atom pair,
+ * other than its pair grid, differ only by a rotation about the A-B axis (each places its C at
+ * phi = 0, Section 2.3) and by the lines moved onto their C (Section 2.2); in the regular cells that
+ * no such grid's moved lines
  * touch their points share (mu, nu, phi) and the distances to A and B.  With the option on, the
  * radial factors of A's and B's functions there are computed once for all of those grids and only
  * the angular factors per grid (grids with Q = 4 and at most 128 cells per axis, all of one pair in
- * one memory pass).  Results are unchanged to rounding.  PS_E_INVALID for other options or values. */
-enum { PS_OPT_SHARE_THIRD_CENTRE = 1 };
+ * one memory pass).  Results are unchanged to rounding.
+ *
+ * PS_OPT_OVERLAP_PASSES (value 0 = off, the default, also chosen by -1; 1 = on): for a job whose
+ * per-point arrays do not fit the budget at once (more than one memory pass), the array budget is split
+ * into two regions taken by alternate passes, and each pass's evaluation runs on a second stream of the
+ * context while the previous pass's contraction runs.  Passes hold half as many grids.  Results are
+ * unchanged to rounding (the reductions of the grids' contributions are grouped differently).  Off by
+ * default: on MI355X the evaluation takes compute units from the contraction rather than filling idle
+ * ones, and the smaller passes cost more than the overlap hides (hydrocarbon job: FP64 equal, mixed
+ * 2.5% slower). */
+enum { PS_OPT_SHARE_THIRD_CENTRE = 1, PS_OPT_OVERLAP_PASSES = 2 };
 int32_t ps_set_option(ps_ctx* ctx, int32_t option, int64_t value);
 
 /* Measured matrix-pipe throughput of the context's device, for reading roofline fractions against

@@ -198,7 +198,7 @@ void compute_layout(const Plan& p, Layout& L) {
   L.items = take(L.items_host.size() * sizeof(int32_t));
   L.status = take(64);
   L.meta_end = o;
-  L.arrays = take(p.max_array_bytes);  // each pass: its arrays, then its partial tiles
+  L.arrays = take(p.max_array_bytes);  // each pass's region: its arrays, then its partial tiles
   L.ws = L.arrays;
   L.out = take((size_t)p.out_elems * sizeof(double));
   L.total = o;
@@ -280,12 +280,22 @@ static void stage_meta(const Plan& p, const Layout& L, char* base, char* host) {
 // The device work of a planned job in segments: 0 = table copy, output clear and the evaluation of
 // pass 0; 2i + 1 = the contraction launches of pass i; 2i + 2 = the reductions of pass i, then the
 // evaluation of pass i + 1, or after the last pass the symmetrisation and the Cholesky factorisation.
+// With overlapped passes the evaluation of pass i + 1 moves into segment 2i + 1: forked onto the
+// slot's side stream before the contraction launches (its region is not the one they read) and joined
+// back after them, so every segment still ends with all of its work ordered on the slot's stream.
 int num_segments(const Plan& p) { return 2 * (int)p.passes.size() + 1; }
+
+int32_t ensure_side(ps_ctx* ctx, Slot& s) {
+  if (!s.side) HIP_TRY(hipStreamCreateWithFlags(&s.side, hipStreamNonBlocking));
+  if (!s.ev_fork) HIP_TRY(hipEventCreateWithFlags(&s.ev_fork, hipEventDisableTiming));
+  if (!s.ev_join) HIP_TRY(hipEventCreateWithFlags(&s.ev_join, hipEventDisableTiming));
+  return PS_OK;
+}
 
 int32_t enqueue_segment(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, int k) {
   (void)ctx;
   char* base = (char*)s.arena;
-  hipStream_t st = s.stream;
+  const hipStream_t st = s.stream;
   double* out = (double*)(base + L.out);
   const GridDev* grids = (const GridDev*)(base + L.grids);
   const double* lines = (const double*)(base + L.lines);
@@ -295,24 +305,32 @@ int32_t enqueue_segment(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, in
   const RedDev* reds = (const RedDev*)(base + L.reds);
   const int32_t* items = (const int32_t*)(base + L.items);
   const bool mixed = p.precision == PS_PREC_MIXED;
-  auto eval = [&](const Pass& ps) {
+  auto eval = [&](const Pass& ps, hipStream_t es) {
     hipError_t e = launch_eval(mixed, segs + ps.seg0, ps.seg1 - ps.seg0, ps.eval_blocks, grids, lines,
                                (const ShellDev*)(base + L.shells), (const MEntry*)(base + L.ments),
-                               (const WColDev*)(base + L.wcols), st);
+                               (const WColDev*)(base + L.wcols), es);
     if (e != hipSuccess) return e;
     return launch_eval_shared(mixed, (const ShareSegDev*)(base + L.ssegs) + ps.sseg0, ps.sseg1 - ps.sseg0,
                               ps.shared_blocks, grids, lines, (const ShellDev*)(base + L.shells),
-                              (const MEntry*)(base + L.ments), st);
+                              (const MEntry*)(base + L.ments), es);
   };
   if (k == 0) {
     HIP_TRY(hipMemcpyAsync(base, s.pinned, L.meta_end, hipMemcpyHostToDevice, st));
     HIP_TRY(launch_fill(out, p.out_elems, 0.0, st));
-    if (!p.passes.empty()) HIP_TRY(eval(p.passes[0]));
+    if (!p.passes.empty()) HIP_TRY(eval(p.passes[0], st));
     return PS_OK;
   }
   const int pi = (k - 1) / 2;
   const Pass& ps = p.passes[pi];
   double* ws = (double*)(base + L.arrays + ps.ws_offset);
+  const bool fork = p.overlap && k % 2 == 1 && pi + 1 < (int)p.passes.size();
+  if (fork) {
+    if (!s.side) return PS_E_DEVICE;  // ensure_side comes first
+    HIP_TRY(hipEventRecord(s.ev_fork, st));
+    HIP_TRY(hipStreamWaitEvent(s.side, s.ev_fork, 0));
+    HIP_TRY(eval(p.passes[pi + 1], s.side));
+    HIP_TRY(hipEventRecord(s.ev_join, s.side));
+  }
   if (k % 2 == 1) {
     // one launch per tile shape: (ab|P) tiles, 64 x 64 tiles, narrow last-column tiles
     for (const auto& lc : ps.launches) {
@@ -324,6 +342,7 @@ int32_t enqueue_segment(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, in
       else
         HIP_TRY(launch_contract_f64(sh.wm, sh.wn, sh.sc, tasks, tiles + lc.tile0, n, ws, st));
     }
+    if (fork) HIP_TRY(hipStreamWaitEvent(st, s.ev_join, 0));
     return PS_OK;
   }
   size_t item_pos = 0;
@@ -333,7 +352,10 @@ int32_t enqueue_segment(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, in
     HIP_TRY(launch_reduce(tasks, reds, items + item_pos, (int)ph.size(), ws, st));
     item_pos += ph.size();
   }
-  if (pi + 1 < (int)p.passes.size()) return eval(p.passes[pi + 1]) == hipSuccess ? PS_OK : PS_E_DEVICE;
+  if (pi + 1 < (int)p.passes.size()) {
+    if (p.overlap) return PS_OK;  // evaluated during this pass's contraction
+    return eval(p.passes[pi + 1], st) == hipSuccess ? PS_OK : PS_E_DEVICE;
+  }
   const int nb = p.n_bf, na = p.n_aux;
   HIP_TRY(launch_symmetrize(out + p.off_S, nb, st));
   HIP_TRY(launch_symmetrize(out + p.off_T, nb, st));
@@ -350,6 +372,10 @@ int32_t enqueue_segment(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, in
 // any graph), so they are measured afresh on every run.
 int32_t enqueue_job(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, const std::vector<hipGraphExec_t>* graphs) {
   hipStream_t st = s.stream;
+  if (p.overlap && !graphs) {
+    int32_t rc = ensure_side(ctx, s);
+    if (rc) return rc;
+  }
   while (s.ev_contract.size() < 2 * p.passes.size()) {
     hipEvent_t e;
     HIP_TRY(hipEventCreate(&e));
@@ -468,15 +494,27 @@ bool share_third_for(const ps_ctx* ctx, int32_t precision) {
   return ctx->share_third < 0 ? precision == PS_PREC_FP64 : ctx->share_third != 0;
 }
 
+bool overlap_passes_for(const ps_ctx* ctx) { return ctx->overlap_passes == 1; }
+
 int32_t plan_job(ps_ctx* ctx, const ps_job* job, Plan& plan, Layout& L) {
   std::string err;
-  int32_t rc = build_plan(job, effective_shape(ctx, job->precision), ctx->ksplit, ctx->budget, &plan, &err,
-                          share_third_for(ctx, job->precision));
+  const TileShape shape = effective_shape(ctx, job->precision);
+  const bool share = share_third_for(ctx, job->precision);
+  int32_t rc = build_plan(job, shape, ctx->ksplit, ctx->budget, &plan, &err, share, overlap_passes_for(ctx));
   if (rc) {
     set_err(ctx, err);
     return rc;
   }
   compute_layout(plan, L);
+  if (plan.overlap && L.total > ctx->budget) {
+    // two regions did not fit after all: one region, passes in series
+    rc = build_plan(job, shape, ctx->ksplit, ctx->budget, &plan, &err, share, false);
+    if (rc) {
+      set_err(ctx, err);
+      return rc;
+    }
+    compute_layout(plan, L);
+  }
   if (L.total > ctx->budget) {
     char buf[200];
     snprintf(buf, sizeof buf, "job needs %.2f GB of device memory, budget is %.2f GB", L.total / 1e9,
@@ -523,6 +561,7 @@ int32_t finish_stats(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, ps_jo
     st->contract_flops = p.contract_flops;
     st->issued_flops = p.issued_flops;
     st->n_passes = (int64_t)p.passes.size();
+    st->passes_overlapped = p.overlap ? 1 : 0;
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, s.ev_start, s.ev_kernels_done) == hipSuccess) st->device_ms = ms;
     double cms = 0.0;
@@ -563,6 +602,12 @@ void slot_free(ps_ctx* ctx, Slot& s) {
   if (s.ev_start) (void)hipEventDestroy(s.ev_start);
   if (s.ev_kernels_done) (void)hipEventDestroy(s.ev_kernels_done);
   if (s.ev_end) (void)hipEventDestroy(s.ev_end);
+  if (s.side) {
+    (void)hipStreamSynchronize(s.side);
+    (void)hipStreamDestroy(s.side);
+  }
+  if (s.ev_fork) (void)hipEventDestroy(s.ev_fork);
+  if (s.ev_join) (void)hipEventDestroy(s.ev_join);
   if (s.own_stream && s.stream) (void)hipStreamDestroy(s.stream);
   s = Slot();
 }
@@ -682,11 +727,17 @@ int32_t ps_mfma_rate(ps_ctx* ctx, int32_t precision, double* tflops) {
 
 int32_t ps_set_option(ps_ctx* ctx, int32_t option, int64_t value) {
   if (!ctx) return PS_E_INVALID;
-  if (option == PS_OPT_SHARE_THIRD_CENTRE && (value == -1 || value == 0 || value == 1)) {
-    ctx->share_third = (int)value;
-    return PS_OK;
+  if (value == -1 || value == 0 || value == 1) {
+    if (option == PS_OPT_SHARE_THIRD_CENTRE) {
+      ctx->share_third = (int)value;
+      return PS_OK;
+    }
+    if (option == PS_OPT_OVERLAP_PASSES) {
+      ctx->overlap_passes = value == 1 ? 1 : 0;
+      return PS_OK;
+    }
   }
-  set_err(ctx, "option: PS_OPT_SHARE_THIRD_CENTRE with value -1, 0 or 1");
+  set_err(ctx, "option: PS_OPT_SHARE_THIRD_CENTRE or PS_OPT_OVERLAP_PASSES with value -1, 0 or 1");
   return PS_E_INVALID;
 }
 
@@ -739,9 +790,11 @@ static std::vector<char> plan_inputs(const ps_ctx* ctx, const ps_job* job) {
   const int tv[4] = {t.wm, t.wn, t.sc, ctx->ksplit};
   put(tv, sizeof tv);
   put(&ctx->budget, sizeof ctx->budget);
-  const char chol = job->PQ_chol != nullptr, share = share_third_for(ctx, job->precision);
+  const char chol = job->PQ_chol != nullptr, share = share_third_for(ctx, job->precision),
+             overlap = overlap_passes_for(ctx);
   put(&chol, 1);
   put(&share, 1);
+  put(&overlap, 1);
   return v;
 }
 
@@ -766,6 +819,10 @@ int32_t ps_compute(ps_ctx* ctx, const ps_job* job, ps_job_stats* st) {
   if (repeat && s.graphs.empty() && !s.graph_failed) {
     // second run of the same plan: capture each segment of its device work (kernels, the table copy;
     // no memset nodes) into a graph of its own, replayed from now on between the timing events
+    if (plan.overlap) {
+      rc = ensure_side(ctx, s);
+      if (rc) return rc;
+    }
     for (int k = 0; k < num_segments(plan) && !s.graph_failed; ++k) {
       hipGraph_t g = nullptr;
       hipGraphExec_t x = nullptr;

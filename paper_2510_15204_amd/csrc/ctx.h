@@ -38,6 +38,10 @@ struct Slot {
   void* pinned = nullptr;
   size_t pinned_size = 0;
   hipEvent_t ev_start = nullptr, ev_kernels_done = nullptr, ev_end = nullptr;
+  // overlapped passes: the next pass's evaluation runs on `side`, forked from and joined back to
+  // `stream` around each contraction segment (created with the first such job)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<hipEvent_t> ev_contract;
   int n_contract = 0;
   bool want_chol = false;
@@ -79,6 +83,7 @@ struct ps_ctx {
   bool shape_explicit = false;  // false: the default shape of the job's precision
   int ksplit = 0;
   int share_third = -1;  // PS_OPT_SHARE_THIRD_CENTRE: -1 automatic (FP64 jobs), 0 off, 1 on
+  int overlap_passes = 0;  // PS_OPT_OVERLAP_PASSES: 0 off (the default, also set by -1), 1 on
   psint::Slot sync_slot;
   std::mutex sync_mu;  // held while ps_compute / ps_autotune use sync_slot; the serving dispatcher
                        // takes an idle sync_slot's arena back when a queued job needs the memory

@@ -12,6 +12,10 @@ void compute_layout(const Plan& p, Layout& L);
 TileShape effective_shape(const ps_ctx* ctx, int32_t precision);
 // Whether a job of this precision on this context uses cross-third-centre reuse.
 bool share_third_for(const ps_ctx* ctx, int32_t precision);
+// Whether jobs on this context that need several memory passes overlap them.
+bool overlap_passes_for(const ps_ctx* ctx);
+// The slot's side stream and fork/join events for overlapped passes (created once).
+int32_t ensure_side(ps_ctx* ctx, Slot& s);
 // Plan the job and size its device layout (PS_E_NOMEM beyond the budget).
 int32_t plan_job(ps_ctx* ctx, const ps_job* job, Plan& plan, Layout& L);
 // Size the slot's arena and pinned staging (plus `extra_pinned` bytes) and stage the tables.

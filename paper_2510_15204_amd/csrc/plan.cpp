@@ -372,7 +372,7 @@ static void xcd_order(std::vector<TileDev>& tiles, int t0, int t1) {
 }
 
 int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_override, size_t budget,
-                   Plan* P, std::string* err, bool share_third) {
+                   Plan* P, std::string* err, bool share_third, bool overlap_passes) {
   int32_t rc = validate_job(job, err);
   if (rc) return rc;
   Plan& p = *P;
@@ -1015,6 +1015,21 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
   // tables (grids, shells, tasks, tiles, pair lists): the pair lists plus a small allowance
   const size_t tables = ((size_t)1 << 20) + budget / 256 + p.ints.size() * 4;
   size_t arr_budget = budget > ws_cap + out_bytes + tables ? budget - ws_cap - out_bytes - tables : 0;
+  // Overlapped passes: each of the two regions holds one pass's arrays, partial tiles and K-split
+  // extras, so a pass gets half of what remains after a second workspace reservation; only for jobs
+  // that need more than one pass anyway, and whose largest grid fits such a pass.
+  {
+    size_t total = 0, largest = 0;
+    for (size_t b : grid_bytes) {
+      total += b;
+      largest = std::max(largest, b);
+    }
+    const size_t half = arr_budget > ws_cap ? (arr_budget - ws_cap) / 2 : 0;
+    if (overlap_passes && total > arr_budget && largest <= half) {
+      p.overlap = true;
+      arr_budget = half;
+    }
+  }
   {
     int g0 = 0;
     while (g0 < (int)p.grids.size()) {
@@ -1299,6 +1314,24 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       p.max_array_bytes = std::max(p.max_array_bytes, ps.ws_offset + (size_t)ws * 8);
       p.max_ws_bytes = std::max(p.max_ws_bytes, (size_t)ws * 8);
     }
+  }
+  if (p.overlap) {
+    // even passes at the start of the array area, odd passes after the largest even one
+    size_t r0 = 0, r1 = 0;
+    for (size_t k = 0; k < p.passes.size(); ++k) {
+      const Pass& ps = p.passes[k];
+      size_t& r = k % 2 ? r1 : r0;
+      r = std::max(r, ps.ws_offset + ps.ws_elems * 8);
+    }
+    r0 = (r0 + 255) / 256 * 256;
+    for (size_t k = 1; k < p.passes.size(); k += 2) {
+      Pass& ps = p.passes[k];
+      ps.region_off = r0;
+      ps.ws_offset += r0;
+      for (auto& a : p.arrays)
+        if (a.grid >= ps.grid0 && a.grid < ps.grid1) a.offset += (int64_t)r0;
+    }
+    p.max_array_bytes = r0 + r1;
   }
   p.contract_flops = 2.0 * p.pair_points;
   return PS_OK;

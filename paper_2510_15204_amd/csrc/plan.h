@@ -41,7 +41,7 @@ struct ArrayHost {
   int grid;
   int nf;
   size_t es = 8;        // bytes per element: 8 (FP64) or 4 (FP32 operands of a mixed job)
-  int64_t offset;       // bytes from the pass's array region start
+  int64_t offset;       // bytes from the array area start (its pass's region start, plus its place there)
   std::vector<int32_t> map;  // column -> caller index (or output selector)
   int64_t map_off;      // int offset in the int table
 };
@@ -89,7 +89,8 @@ struct Pass {
   int64_t eval_blocks;
   size_t array_bytes;
   size_t ws_elems;
-  size_t ws_offset;     // bytes from the region start to the pass's partial tiles (after its arrays)
+  size_t ws_offset;     // bytes from the array area's start to the pass's partial tiles (after its arrays)
+  size_t region_off = 0;  // bytes from the array area's start to the pass's region (overlapped passes)
 };
 
 struct Plan {
@@ -125,7 +126,11 @@ struct Plan {
   double contract_flops = 0.0;
   double issued_flops = 0.0;
   int64_t n_points = 0;
-  size_t max_array_bytes = 0;  // region per pass: arrays, then partial tiles (max over passes)
+  size_t max_array_bytes = 0;  // array area: one region (arrays, then partial tiles) per pass, or two
+                               // alternating regions when passes overlap
+  // Overlapped passes: pass i + 1's evaluation runs while pass i's contraction reads its own region,
+  // so consecutive passes take alternate halves of the array budget.
+  bool overlap = false;
   size_t max_ws_bytes = 0;     // partial tiles alone (max over passes)
   size_t meta_bytes = 0;
 };
@@ -133,9 +138,10 @@ struct Plan {
 // Validate the job; returns PS_OK or an error code with a message.
 int32_t validate_job(const ps_job* job, std::string* err);
 
-// Build the full plan.  `budget` bounds array + workspace bytes per pass.
+// Build the full plan.  `budget` bounds array + workspace bytes per pass.  With `overlap_passes`, a job
+// that needs more than one memory pass is planned with two alternating regions (Plan::overlap).
 int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_override, size_t budget,
-                   Plan* plan, std::string* err, bool share_third = false);
+                   Plan* plan, std::string* err, bool share_third = false, bool overlap_passes = false);
 
 // Grid construction alone (used by the inspection hook).
 int32_t build_grid(const ps_atom* atoms, int n_atoms, int A, int B, int C, const ps_grid_spec& spec,

@@ -19,6 +19,7 @@ PS_OK, PS_E_INVALID, PS_E_UNSUPPORTED, PS_E_NOMEM, PS_E_DEVICE, PS_E_NOT_PD, PS_
     PS_E_QUEUE_FULL, PS_E_NOT_FOUND = 0, -1, -2, -3, -4, -5, -6, -7, -8
 PREC = {"fp64": 0, "mixed": 1}
 PS_OPT_SHARE_THIRD_CENTRE = 1
+PS_OPT_OVERLAP_PASSES = 2
 OUTPUTS = ("S", "T", "V", "PQ", "PQ_chol", "abP")
 
 
@@ -63,7 +64,8 @@ class JobStats(C.Structure):
     _fields_ = [("n_grids", C.c_int64), ("n_points", C.c_int64), ("pair_points", C.c_double),
                 ("queue_ms", C.c_double), ("device_ms", C.c_double), ("total_ms", C.c_double),
                 ("contract_ms", C.c_double), ("contract_flops", C.c_double), ("issued_flops", C.c_double),
-                ("n_passes", C.c_int64), ("graph_replay", C.c_int64)]
+                ("n_passes", C.c_int64), ("graph_replay", C.c_int64),
+                ("passes_overlapped", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

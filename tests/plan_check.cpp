@@ -2,7 +2,8 @@
 // element of every task is covered by exactly one reduction item, each item's K splits tile the
 // grid's point chunks [0, nchunks) in order without gaps or overlaps, every tile sits in one launch
 // whose tile shape holds it, the issued FLOPs add up, and the splits of one item are even.
-// Usage: plan_check <job file> <precision 0|1> <resident work-groups per launch> <budget GB>
+// Usage: plan_check <job file> <precision 0|1> <resident work-groups per launch> <budget GB> [options]
+// (options: "share" and/or "overlap", e.g. "share,overlap").
 // Job file: natoms, atoms (x y z Z), nbf, basis rows (atom n l m zeta), naux, aux rows, grid spec
 // (n_mu n_nu n_phi q n_sp c1_scale c1_exp), npg, per-pair specs (A B + the 7 spec fields).
 #include <cstdio>
@@ -71,10 +72,31 @@ int main(int argc, char** argv) {
   const size_t budget = (size_t)(atof(argv[4]) * 1e9);
   Plan p;
   std::string err;
-  const bool share = argc > 5 && std::string(argv[5]) == "share";
-  if (build_plan(&job, ts, 0, budget, &p, &err, share) != PS_OK) {
+  const std::string opts = argc > 5 ? argv[5] : "";
+  const bool share = opts.find("share") != std::string::npos;
+  const bool overlap = opts.find("overlap") != std::string::npos;
+  if (build_plan(&job, ts, 0, budget, &p, &err, share, overlap) != PS_OK) {
     printf("FAIL plan %s\n", err.c_str());
     return 1;
+  }
+
+  // array area: each pass's arrays and partial tiles inside its region, within the area; with
+  // overlapped passes, consecutive passes' regions disjoint (one is written while the other is read)
+  if (p.overlap && (!overlap || p.passes.size() < 2)) return fail("overlap without several passes");
+  std::vector<std::pair<size_t, size_t>> region(p.passes.size());
+  for (int k = 0; k < (int)p.passes.size(); ++k) {
+    const Pass& ps = p.passes[k];
+    const size_t end = ps.ws_offset + ps.ws_elems * 8;
+    if (ps.ws_offset < ps.region_off || end > p.max_array_bytes) return fail("pass region", k);
+    if (!p.overlap && ps.region_off != 0) return fail("region offset without overlap", k);
+    region[k] = {ps.region_off, end};
+    for (const auto& a : p.arrays) {
+      if (a.grid < ps.grid0 || a.grid >= ps.grid1) continue;
+      const size_t lo = (size_t)a.offset, hi = lo + (size_t)a.nf * p.grids[a.grid].dev.npad * a.es;
+      if (lo < ps.region_off || hi > ps.ws_offset || lo % 256) return fail("array outside its pass's region", k, a.grid);
+    }
+    if (p.overlap && k > 0 && region[k].first < region[k - 1].second && region[k - 1].first < region[k].second)
+      return fail("consecutive passes share memory", k);
   }
 
   // tiles by (pass, partial-tile offset): each pass reuses the workspace, each offset once per pass
@@ -187,6 +209,7 @@ int main(int argc, char** argv) {
   for (size_t si = 0; si < p.segs.size(); ++si)
     if ((p.segs[si].dev.skip != 0) != (skipped_by[si] == 1)) return fail("segment skips without one share", (long)si);
   if (share && kept == 0) return fail("no share kept");
-  printf("ok %zu tiles %zu items %zu passes %zu shares\n", p.tiles.size(), p.reds.size(), p.passes.size(), kept);
+  printf("ok %zu tiles %zu items %zu passes %zu shares%s\n", p.tiles.size(), p.reds.size(), p.passes.size(), kept,
+         p.overlap ? " overlapped" : "");
   return 0;
 }

@@ -319,6 +319,57 @@ def test_memory_passes_match_single_pass():
     big.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_overlapped_passes_match_serial_passes(prec):
+    """PS_OPT_OVERLAP_PASSES: under a budget that needs several memory passes, the overlapped plan
+    (alternate regions, each pass's evaluation on the side stream during the previous contraction) gives
+    the serial plan's results up to the grouping of the grids' sums, on its first run, its captured
+    second run and its replayed third; and the same job served through the dispatcher agrees."""
+    xyz = np.array([[0.0, 0.0, 0.0], [1.9, 0.2, 0.0], [-0.4, 1.8, 0.3], [0.6, -0.5, 2.0]])
+    basis = [[a, 1, 0, 0, 1.2 + 0.3 * a] for a in range(4)] + [[a, 2, 1, 1, 1.0] for a in range(4)]
+    aux = [[a, 1, 0, 0, 2.5] for a in range(4)] + [[a, 2, 1, -1, 2.0] for a in range(4)]
+    job = MiniJob(xyz, [6, 1, 8, 1], basis, aux, Spec(10, 10, 8, 4, 3))
+    probe = psint.Context(0)
+    need = probe.plan_work(job, precision=prec)["device_bytes"]
+    probe.close()
+    c = None
+    for frac in (0.6, 0.5, 0.4, 0.3, 0.25, 0.2, 0.15, 0.1):
+        # a budget under which the job needs several passes and its largest grid fits half a region
+        budget = int(need * frac)
+        c = psint.Context(0, budget_bytes=budget)
+        c.set_option(psint.PS_OPT_OVERLAP_PASSES, 1)
+        try:
+            first = c.compute(job, precision=prec)
+        except psint.PsError as e:
+            assert e.status == psint.PS_E_NOMEM
+            first = None
+        if first is not None and first[1]["passes_overlapped"]:
+            break
+        c.close()
+        c = None
+    assert c is not None, "no budget gave overlapped passes"
+    serial = psint.Context(0, budget_bytes=budget)
+    serial.set_option(psint.PS_OPT_OVERLAP_PASSES, 0)
+    ref, st_ref, _ = serial.compute(job, precision=prec)
+    serial.close()
+    try:
+        runs = [first] + [c.compute(job, precision=prec) for _ in range(2)]
+        _say(f"{prec}: budget {budget / 1e6:.0f} MB, serial {st_ref['n_passes']} passes, overlapped "
+             f"{runs[0][1]['n_passes']}; graph replay {[r[1]['graph_replay'] for r in runs]}")
+        assert st_ref["n_passes"] >= 2 and st_ref["passes_overlapped"] == 0
+        assert runs[2][1]["graph_replay"] == 1 and runs[2][1]["passes_overlapped"] == 1
+        served, _, _ = c.wait(c.submit(job, precision=prec), timeout_us=60_000_000)
+    finally:
+        c.close()
+    for i, (got, _, _) in enumerate(runs + [(served, None, None)]):
+        for k in psint.OUTPUTS:
+            scale = max(np.max(np.abs(ref[k])), 1e-300)
+            d = np.max(np.abs(got[k] - ref[k]))
+            assert d <= 1e-12 * scale, (i, k, d)
+            if i:
+                assert np.array_equal(got[k], runs[0][0][k]), (i, k)
+
+
 def test_device_pool_reuse_across_job_sizes():
     """One context runs jobs of growing and shrinking size (its arena ranges move within the device
     pool; one job needs a quarter of the budget or more and reserves the rest of it; one needs two

@@ -2,7 +2,9 @@
 tests/plan_check.cpp) on the benchmark workloads and under a small memory budget: every output
 element of every task is covered by exactly one reduction item, each item's K splits tile its grid's
 point chunks in order and evenly, every tile sits in a launch whose shape holds it, and the issued
-FLOPs add up; with cross-third-centre reuse, the shared segments and the cells their members skip."""
+FLOPs add up, and every pass's arrays and partial tiles lie in its own region (disjoint from the next
+pass's when passes overlap); with cross-third-centre reuse, the shared segments and the cells their
+members skip."""
 import os
 import subprocess
 
@@ -45,6 +47,10 @@ def _write_job(job, path):
     ("hydrocarbon9", 0, 246.0, "share"),  # cross-third-centre reuse: shared segments, skip masks
     ("hydrocarbon9", 1, 246.0, "share"),
     ("hydrocarbon9", 0, 40.0, "share"),   # many passes: shares split by a pass boundary are dropped
+    ("hydrocarbon9", 0, 246.0, "share,overlap"),  # overlapped passes: alternating disjoint regions
+    ("hydrocarbon9", 1, 246.0, "overlap"),
+    ("triatomic_qz", 0, 10.0, "overlap"),
+    ("triatomic_qz", 0, 200.0, "overlap"),  # one pass: nothing to overlap
 ])
 def test_plan_invariants(checker, name, prec, budget_gb, share):
     exe, d = checker
@@ -55,3 +61,5 @@ def test_plan_invariants(checker, name, prec, budget_gb, share):
     out = subprocess.run(args, capture_output=True, text=True, timeout=300)
     print(out.stdout.strip())
     assert out.returncode == 0 and out.stdout.startswith("ok"), out.stdout + out.stderr
+    if "overlap" in share:
+        assert ("overlapped" in out.stdout) == (budget_gb < 200.0 or name == "hydrocarbon9"), out.stdout
