@@ -480,6 +480,7 @@ TileShape effective_shape(const ps_ctx* ctx, int32_t precision) {
     t.slots2 = resident(2, 2, t.sc);
     for (int w = 1; w < t.wn && w <= 3; ++w) t.slots_n[w] = resident(t.wm, w, t.sc);
     t.slots2n = resident(2, 1, t.sc);
+    for (int w = 1; w <= t.wn && w <= 4 && t.wm > 1; ++w) t.slots_short[w] = resident(1, w, t.sc);
     if (mixed) {  // the FP64 two-index launches of a mixed job
       t.slots2_f64 = resident_of(false, 2, 2, t.sc);
       t.slots2n_f64 = resident_of(false, 2, 1, t.sc);

@@ -1214,6 +1214,8 @@ static hipError_t launch_contract_any(int wm, int wn, int sc, const TaskDev* tas
   PS_SHAPE(4, 2, 1) PS_SHAPE(4, 2, 2) PS_SHAPE(2, 4, 1) PS_SHAPE(2, 4, 2)
   PS_SHAPE(4, 1, 1) PS_SHAPE(4, 1, 2) PS_SHAPE(4, 3, 1) PS_SHAPE(4, 3, 2)
   PS_SHAPE(2, 1, 1) PS_SHAPE(2, 1, 2) PS_SHAPE(2, 3, 1) PS_SHAPE(2, 3, 2)
+  PS_SHAPE(1, 1, 1) PS_SHAPE(1, 1, 2) PS_SHAPE(1, 2, 1) PS_SHAPE(1, 2, 2)
+  PS_SHAPE(1, 3, 1) PS_SHAPE(1, 3, 2) PS_SHAPE(1, 4, 1) PS_SHAPE(1, 4, 2)
 #undef PS_SHAPE
   return hipErrorInvalidValue;
 }
@@ -1239,6 +1241,8 @@ int contract_resident_workgroups(bool mixed, int wm, int wn, int sc) {
   PS_SHAPE(4, 2, 1) PS_SHAPE(4, 2, 2) PS_SHAPE(2, 4, 1) PS_SHAPE(2, 4, 2)
   PS_SHAPE(4, 1, 1) PS_SHAPE(4, 1, 2) PS_SHAPE(4, 3, 1) PS_SHAPE(4, 3, 2)
   PS_SHAPE(2, 1, 1) PS_SHAPE(2, 1, 2) PS_SHAPE(2, 3, 1) PS_SHAPE(2, 3, 2)
+  PS_SHAPE(1, 1, 1) PS_SHAPE(1, 1, 2) PS_SHAPE(1, 2, 1) PS_SHAPE(1, 2, 2)
+  PS_SHAPE(1, 3, 1) PS_SHAPE(1, 3, 2) PS_SHAPE(1, 4, 1) PS_SHAPE(1, 4, 2)
 #undef PS_SHAPE
   return 0;
 }

@@ -1127,11 +1127,20 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       // when that tile is at most 32 w wide (e.g. 345 columns = 128 + 128 + 96 instead of 3 x 128)
       // (group 5: the 64 x 64 shape narrowed to 32 columns, likewise for its tasks' last tiles;
       // groups 6 and 7: the 64 x 64 and 64 x 32 shapes in FP64, for the two-index tasks of a mixed job)
-      constexpr int NG = 8;
-      TileShape gshape[NG] = {shape, shape2, shape, shape, shape, shape2, shape2, shape2};
+      // groups: 0 main shape, 1 the 64 x 64 shape, 2-4 the main shape narrowed to 32, 64, 96 columns,
+      // 5 the 64 x 32 shape, 6-7 the FP64 64 x 64 and 64 x 32 shapes of a mixed job, 8-11 32-row
+      // shapes 32 x (32, 64, 96, 128) for the main shape's short row tiles
+      constexpr int NG = 12;
+      TileShape gshape[NG] = {shape, shape2, shape, shape, shape, shape2, shape2, shape2,
+                              shape, shape, shape, shape};
       for (int w = 1; w <= 3; ++w) {
         gshape[1 + w].wn = w;
         gshape[1 + w].slots = shape.slots_n[w];
+      }
+      for (int w = 1; w <= 4; ++w) {
+        gshape[7 + w].wm = 1;
+        gshape[7 + w].wn = w;
+        gshape[7 + w].slots = shape.slots_short[w];
       }
       gshape[5].wn = 1;
       gshape[5].slots = shape.slots2n;
@@ -1139,7 +1148,7 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       gshape[7].wn = 1;
       gshape[7].slots = shape.slots2n_f64;
       std::vector<Item> items[NG];
-      double total_cost[NG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      double total_cost[NG] = {};
       for (int t = ps.task0; t < ps.task1; ++t) {
         TaskHost& th = p.tasks[t];
         const int grp0 = (mixed && th.out_kind != 4) ? 6 : (small_task[t] ? 1 : 0);
@@ -1173,6 +1182,11 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
             if (grp0 == 0 && w < shape.wn) grp = 1 + w;
             if (grp0 == 1 && w < shape2.wn) grp = 5;
             if (grp0 == 6 && w < shape2.wn) grp = 7;
+            // a task's last row tile when it holds a quarter of the main shape's rows or fewer (e.g. 4
+            // of 128): a 32-row shape issues a quarter of the MFMAs
+            if (grp0 == 0 && shape.wm > 1 && w <= 4 && 4 * it.nrows <= shape.bm() &&
+                it.nu + it.nv <= gshape[7 + w].maxuv())
+              grp = 7 + w;
             total_cost[grp] += it.cost;
             items[grp].push_back(it);
           }
@@ -1183,10 +1197,11 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       ps.launches.clear();
       ps.tile0 = (int)p.tiles.size();
       int n_narrow = 0, n_second = 0;
-      for (int grp : {2, 3, 4, 5, 7}) n_narrow += items[grp].empty() ? 0 : 1;
+      for (int grp : {2, 3, 4, 5, 7, 8, 9, 10, 11}) n_narrow += items[grp].empty() ? 0 : 1;
       for (int grp : {1, 6}) n_second += items[grp].empty() ? 0 : 1;
-      // launch order: main, narrow main, 64 x 64, narrow 64 x 64, then the FP64 ones of a mixed job
-      const int order[NG] = {0, 2, 3, 4, 1, 5, 6, 7};
+      // launch order: main, narrow main, 32-row, 64 x 64, narrow 64 x 64, then the FP64 ones of a
+      // mixed job
+      const int order[NG] = {0, 2, 3, 4, 8, 9, 10, 11, 1, 5, 6, 7};
       for (int oi = 0; oi < NG; ++oi) {
         const int grp = order[oi];
         if (items[grp].empty()) continue;
@@ -1305,7 +1320,7 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
           p.reds.push_back(rd);
         }
         xcd_order(p.tiles, tg0, (int)p.tiles.size());
-        ps.launches.push_back({tg0, (int)p.tiles.size(), sh, grp >= 6});
+        ps.launches.push_back({tg0, (int)p.tiles.size(), sh, grp == 6 || grp == 7});
       }
       ps.tile1 = (int)p.tiles.size();
       ps.ws_elems = (size_t)ws;

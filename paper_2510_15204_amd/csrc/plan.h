@@ -22,6 +22,7 @@ struct TileShape {
   int slots_n[4] = {0, 0, 0, 0};          // the same for this shape narrowed to wn = 1..3 (index wn)
   int slots2n = 0;                        // the same for the 64 x 32 shape
   int slots2_f64 = 0, slots2n_f64 = 0;    // 64 x 64 and 64 x 32 in FP64 within a mixed job
+  int slots_short[5] = {0, 0, 0, 0, 0};   // the 32-row shapes (wm = 1) of width wn = 1..4 (index wn)
   int bm() const { return 32 * wm; }
   int bn() const { return 32 * wn; }
   int maxuv() const { return bm() + 4; }  // staged U + V columns per tile

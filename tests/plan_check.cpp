@@ -69,6 +69,7 @@ int main(int argc, char** argv) {
   const int slots = atoi(argv[3]);
   ts.slots = ts.slots2 = ts.slots2n = ts.slots2_f64 = ts.slots2n_f64 = slots;
   for (int w = 1; w < 4; ++w) ts.slots_n[w] = slots;
+  for (int w = 1; w <= 4; ++w) ts.slots_short[w] = slots;
   const size_t budget = (size_t)(atof(argv[4]) * 1e9);
   Plan p;
   std::string err;
