@@ -20,13 +20,13 @@ hipError_t launch_eval_shared(bool fp32, const ShareSegDev* segs, int nseg, int6
 hipError_t launch_eval(bool fp32, const SegDev* segs, int nseg, int64_t nblocks, const GridDev* grids,
                        const double* lines, const ShellDev* shells, const MEntry* ments, const WColDev* wcols,
                        hipStream_t st);
-hipError_t launch_contract_f64(int wm, int wn, int sc, const TaskDev* tasks, const TileDev* tiles, int ntiles,
-                               double* ws, hipStream_t st);
-hipError_t launch_contract_mixed(int wm, int wn, int sc, const TaskDev* tasks, const TileDev* tiles, int ntiles,
-                                 double* ws, hipStream_t st);
+hipError_t launch_contract_f64(int wm, int wn, int sc, int wr, const TaskDev* tasks, const TileDev* tiles,
+                               int ntiles, double* ws, hipStream_t st);
+hipError_t launch_contract_mixed(int wm, int wn, int sc, int wr, const TaskDev* tasks, const TileDev* tiles,
+                                 int ntiles, double* ws, hipStream_t st);
 hipError_t launch_reduce(const TaskDev* tasks, const RedDev* reds, const int32_t* items, int nitems,
                          const double* ws, hipStream_t st);
-int contract_resident_workgroups(bool mixed, int wm, int wn, int sc);
+int contract_resident_workgroups(bool mixed, int wm, int wn, int sc, int wr);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_mfma_rate(bool fp64, int blocks, int iters, double* out, hipStream_t st);
 hipError_t launch_symmetrize(double* X, int n, hipStream_t st);
@@ -338,9 +338,9 @@ int32_t enqueue_segment(ps_ctx* ctx, Slot& s, const Plan& p, const Layout& L, in
       if (n <= 0) continue;
       const TileShape& sh = lc.shape;
       if (mixed && !lc.f64)
-        HIP_TRY(launch_contract_mixed(sh.wm, sh.wn, sh.sc, tasks, tiles + lc.tile0, n, ws, st));
+        HIP_TRY(launch_contract_mixed(sh.wm, sh.wn, sh.sc, sh.wr, tasks, tiles + lc.tile0, n, ws, st));
       else
-        HIP_TRY(launch_contract_f64(sh.wm, sh.wn, sh.sc, tasks, tiles + lc.tile0, n, ws, st));
+        HIP_TRY(launch_contract_f64(sh.wm, sh.wn, sh.sc, sh.wr, tasks, tiles + lc.tile0, n, ws, st));
     }
     if (fork) HIP_TRY(hipStreamWaitEvent(st, s.ev_join, 0));
     return PS_OK;
@@ -466,24 +466,26 @@ TileShape effective_shape(const ps_ctx* ctx, int32_t precision) {
   t.slots = t.slots2 = 0;
   if (ctx) {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int, int>, int> cache;
+    static std::map<std::tuple<int, int, int, int, int, int>, int> cache;
     const bool mixed = precision == PS_PREC_MIXED;
-    auto resident_of = [&](bool mx, int wm, int wn, int sc) {
-      const auto key = std::make_tuple(ctx->device, (int)mx, wm, wn, sc);
+    auto resident_of = [&](bool mx, int wm, int wn, int sc, int wr) {
+      const auto key = std::make_tuple(ctx->device, (int)mx, wm, wn, sc, wr);
       auto it = cache.find(key);
-      if (it == cache.end()) it = cache.emplace(key, contract_resident_workgroups(mx, wm, wn, sc)).first;
+      if (it == cache.end()) it = cache.emplace(key, contract_resident_workgroups(mx, wm, wn, sc, wr)).first;
       return it->second;
     };
-    auto resident = [&](int wm, int wn, int sc) { return resident_of(mixed, wm, wn, sc); };
+    auto resident = [&](int wm, int wn, int sc, int wr = 2) { return resident_of(mixed, wm, wn, sc, wr); };
     std::lock_guard<std::mutex> g(mu);
-    t.slots = resident(t.wm, t.wn, t.sc);
+    t.slots = resident(t.wm, t.wn, t.sc, t.wr);
     t.slots2 = resident(2, 2, t.sc);
     for (int w = 1; w < t.wn && w <= 3; ++w) t.slots_n[w] = resident(t.wm, w, t.sc);
     t.slots2n = resident(2, 1, t.sc);
-    for (int w = 1; w <= t.wn && w <= 4 && t.wm > 1; ++w) t.slots_short[w] = resident(1, w, t.sc);
+    for (int w = 1; w <= 4; ++w) t.slots_short[w] = resident(1, w, t.sc);
+    for (int k = 0; k < 4; ++k) t.slots_tall[k] = resident(2, 2 * k + 1, t.sc, 4);
     if (mixed) {  // the FP64 two-index launches of a mixed job
-      t.slots2_f64 = resident_of(false, 2, 2, t.sc);
-      t.slots2n_f64 = resident_of(false, 2, 1, t.sc);
+      t.slots2_f64 = resident_of(false, 2, 2, t.sc, 2);
+      t.slots2n_f64 = resident_of(false, 2, 1, t.sc, 2);
+      for (int w = 1; w <= 2; ++w) t.slots_short_f64[w] = resident_of(false, 1, w, t.sc, 2);
     }
   }
   return t;

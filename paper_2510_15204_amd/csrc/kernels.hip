@@ -507,8 +507,9 @@ __global__ __launch_bounds__(256) void eval_shared_kernel(const ShareSegDev* __r
 }
 
 // ------------------------------------------------------------------------------------------------
-// Contraction kernels.  256 threads = 4 waves in 2 x 2; wave (wm, wn) owns WM x WN MFMA blocks of
-// 16 x 16.  Points are consumed in stages of SC storage chunks (SC * 16 points).  Each stage's U, V
+// Contraction kernels.  256 threads = 4 waves, WR along the rows and 4 / WR along the columns (2 x 2,
+// or 4 x 1 for tiles whose width is an odd number of 16-column blocks); wave (wm, wn) owns WM x WN
+// MFMA blocks of 16 x 16.  Points are consumed in stages of SC storage chunks (SC * 16 points).  Each stage's U, V
 // and Y columns sit in LDS as rows of SC * 16 values padded by 4 (bank-conflict-free operand reads);
 // two LDS buffers alternate, so one barrier per stage suffices: while the MFMAs of stage s run on one
 // buffer, the registers holding stage s+1 (loaded during stage s-1) are written to the other buffer
@@ -518,9 +519,10 @@ __global__ __launch_bounds__(256) void eval_shared_kernel(const ShareSegDev* __r
 // v_mfma_f64_16x16x4 result register r of lane l = D[4r + l/16][l%16];
 // v_mfma_f32_16x16x4f32 result register r of lane l = D[4(l/16) + r][l%16].
 // ------------------------------------------------------------------------------------------------
-template <typename T, int WM, int WN, int SC_>
+template <typename T, int WM, int WN, int SC_, int WR = 2>
 struct ContractCfg {
-  static constexpr int BM = 32 * WM, BN = 32 * WN;
+  static constexpr int WC = 4 / WR;                     // waves along the columns
+  static constexpr int BM = 16 * WM * WR, BN = 16 * WN * WC;
   static constexpr int SC = SC_;                        // storage chunks per stage
   static constexpr int KS = SC * KC;                    // points per stage
   // padded LDS row: FP64 rows 34 doubles (68 words: 16 consecutive rows at the same k fall in distinct
@@ -543,10 +545,10 @@ struct ContractCfg {
 // rows [0, nu+nv) or the Y rows [MAXUV, MAXUV+np).  Each thread's source offset for every copy it
 // issues is computed once per tile; per stage only the chunk base moves.  The copies of stage s+1
 // are spread between the MFMA steps of stage s so their address work hides under the matrix pipe.
-template <typename T, int WM, int WN, int SC_>
+template <typename T, int WM, int WN, int SC_, int WR>
 __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, const TileDev& t,
                                               __attribute__((address_space(3))) T* lds, double* __restrict__ ws) {
-  typedef ContractCfg<T, WM, WN, SC_> Cf;
+  typedef ContractCfg<T, WM, WN, SC_, WR> Cf;
   constexpr int BN = Cf::BN, LDK = Cf::LDK, MAXUV = Cf::MAXUV, KS = Cf::KS, SC = Cf::SC, BUF = Cf::BUF;
   constexpr int SLOTS = Cf::SLOTS, DSLOTS = Cf::DSLOTS, VN = Cf::VN;
   constexpr int NCUV = (MAXUV * SLOTS + 255) / 256;  // copies per thread per stage, U+V region (max)
@@ -561,7 +563,7 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
   constexpr bool ROWOUTER = !F64 && WM * WN > 8;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform, lets tests below be scalar
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / Cf::WC, wn = wave % Cf::WC;
   const int kl = lane >> 4;
 
   // Rows beyond nrows and columns beyond np are computed on whatever their (in-bounds) LDS rows hold
@@ -840,25 +842,25 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
       }
 }
 
-template <int WM, int WN, int SC>
+template <int WM, int WN, int SC, int WR>
 __global__ __launch_bounds__(256, 1) void contract_f64(const TaskDev* __restrict__ tasks,
                                                        const TileDev* __restrict__ tiles,
                                                        double* __restrict__ ws) {
   extern __shared__ __attribute__((aligned(16))) double smem_d[];
   const TileDev t = tiles[blockIdx.x];
-  contract_body<double, WM, WN, SC>(tasks[t.task], t, (__attribute__((address_space(3))) double*)smem_d, ws);
+  contract_body<double, WM, WN, SC, WR>(tasks[t.task], t, (__attribute__((address_space(3))) double*)smem_d, ws);
 }
 
 // Two waves per SIMD asked of the compiler: the widest FP32 tile then keeps its FP64 accumulators
 // and operands in VGPRs rather than splitting them into AGPRs (measured 2% faster than leaving the
 // allocation free).
-template <int WM, int WN, int SC>
+template <int WM, int WN, int SC, int WR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void contract_mixed(const TaskDev* __restrict__ tasks,
                                                          const TileDev* __restrict__ tiles,
                                                          double* __restrict__ ws) {
   extern __shared__ __attribute__((aligned(16))) float smem_f[];
   const TileDev t = tiles[blockIdx.x];
-  contract_body<float, WM, WN, SC>(tasks[t.task], t, (__attribute__((address_space(3))) float*)smem_f, ws);
+  contract_body<float, WM, WN, SC, WR>(tasks[t.task], t, (__attribute__((address_space(3))) float*)smem_f, ws);
 }
 
 // Sum the splits of each reduction item in order and scatter into the FP64 output buffer.  Partial
@@ -1188,44 +1190,50 @@ hipError_t launch_eval_shared(bool fp32, const ShareSegDev* segs, int nseg, int6
   return hipGetLastError();
 }
 
-template <typename T, int WM, int WN, int SC>
+template <typename T, int WM, int WN, int SC, int WR>
 static hipError_t launch_contract_t(const TaskDev* tasks, const TileDev* tiles, int ntiles, double* ws,
                                     hipStream_t st) {
-  constexpr int lds = ContractCfg<T, WM, WN, SC>::LDS_BYTES;
+  constexpr int lds = ContractCfg<T, WM, WN, SC, WR>::LDS_BYTES;
   static_assert(lds <= 160 * 1024, "LDS budget");
-  const void* fn = sizeof(T) == 8 ? (const void*)contract_f64<WM, WN, SC> : (const void*)contract_mixed<WM, WN, SC>;
+  const void* fn = sizeof(T) == 8 ? (const void*)contract_f64<WM, WN, SC, WR>
+                                  : (const void*)contract_mixed<WM, WN, SC, WR>;
   // once per instantiation (a function-local static is initialised once, also with concurrent callers)
   static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (attr != hipSuccess) return attr;
   if constexpr (sizeof(T) == 8)
-    hipLaunchKernelGGL((contract_f64<WM, WN, SC>), dim3(ntiles), dim3(256), lds, st, tasks, tiles, ws);
+    hipLaunchKernelGGL((contract_f64<WM, WN, SC, WR>), dim3(ntiles), dim3(256), lds, st, tasks, tiles, ws);
   else
-    hipLaunchKernelGGL((contract_mixed<WM, WN, SC>), dim3(ntiles), dim3(256), lds, st, tasks, tiles, ws);
+    hipLaunchKernelGGL((contract_mixed<WM, WN, SC, WR>), dim3(ntiles), dim3(256), lds, st, tasks, tiles, ws);
   return hipGetLastError();
 }
 
+// Shapes built: (wm, wn, stage chunks) in the 2 x 2 wave arrangement, and the 4 x 1 arrangement with
+// wm = 2 (128 rows) and odd wn (16 to 112 columns).
+#define PS_SHAPES(X)                                                                            \
+  X(4, 4, 1, 2) X(4, 4, 2, 2) X(2, 2, 1, 2) X(2, 2, 2, 2) X(4, 2, 1, 2) X(4, 2, 2, 2) X(2, 4, 1, 2) \
+  X(2, 4, 2, 2) X(4, 1, 1, 2) X(4, 1, 2, 2) X(4, 3, 1, 2) X(4, 3, 2, 2) X(2, 1, 1, 2) X(2, 1, 2, 2) \
+  X(2, 3, 1, 2) X(2, 3, 2, 2) X(1, 1, 1, 2) X(1, 1, 2, 2) X(1, 2, 1, 2) X(1, 2, 2, 2) X(1, 3, 1, 2) \
+  X(1, 3, 2, 2) X(1, 4, 1, 2) X(1, 4, 2, 2) X(2, 1, 1, 4) X(2, 1, 2, 4) X(2, 3, 1, 4) X(2, 3, 2, 4) \
+  X(2, 5, 1, 4) X(2, 5, 2, 4) X(2, 7, 1, 4) X(2, 7, 2, 4)
+
 template <typename T>
-static hipError_t launch_contract_any(int wm, int wn, int sc, const TaskDev* tasks, const TileDev* tiles, int ntiles,
-                                      double* ws, hipStream_t st) {
+static hipError_t launch_contract_any(int wm, int wn, int sc, int wr, const TaskDev* tasks, const TileDev* tiles,
+                                      int ntiles, double* ws, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-#define PS_SHAPE(a, b, c) \
-  if (wm == a && wn == b && sc == c) return launch_contract_t<T, a, b, c>(tasks, tiles, ntiles, ws, st);
-  PS_SHAPE(4, 4, 1) PS_SHAPE(4, 4, 2) PS_SHAPE(2, 2, 1) PS_SHAPE(2, 2, 2)
-  PS_SHAPE(4, 2, 1) PS_SHAPE(4, 2, 2) PS_SHAPE(2, 4, 1) PS_SHAPE(2, 4, 2)
-  PS_SHAPE(4, 1, 1) PS_SHAPE(4, 1, 2) PS_SHAPE(4, 3, 1) PS_SHAPE(4, 3, 2)
-  PS_SHAPE(2, 1, 1) PS_SHAPE(2, 1, 2) PS_SHAPE(2, 3, 1) PS_SHAPE(2, 3, 2)
-  PS_SHAPE(1, 1, 1) PS_SHAPE(1, 1, 2) PS_SHAPE(1, 2, 1) PS_SHAPE(1, 2, 2)
-  PS_SHAPE(1, 3, 1) PS_SHAPE(1, 3, 2) PS_SHAPE(1, 4, 1) PS_SHAPE(1, 4, 2)
+#define PS_SHAPE(a, b, c, d) \
+  if (wm == a && wn == b && sc == c && wr == d) return launch_contract_t<T, a, b, c, d>(tasks, tiles, ntiles, ws, st);
+  PS_SHAPES(PS_SHAPE)
 #undef PS_SHAPE
   return hipErrorInvalidValue;
 }
 
 // Work-groups of one contraction shape resident on the current device at once (occupancy x CUs),
 // 0 when the runtime cannot tell.
-template <typename T, int WM, int WN, int SC>
+template <typename T, int WM, int WN, int SC, int WR>
 static int resident_t() {
-  constexpr int lds = ContractCfg<T, WM, WN, SC>::LDS_BYTES;
-  const void* fn = sizeof(T) == 8 ? (const void*)contract_f64<WM, WN, SC> : (const void*)contract_mixed<WM, WN, SC>;
+  constexpr int lds = ContractCfg<T, WM, WN, SC, WR>::LDS_BYTES;
+  const void* fn = sizeof(T) == 8 ? (const void*)contract_f64<WM, WN, SC, WR>
+                                  : (const void*)contract_mixed<WM, WN, SC, WR>;
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return 0;
   int per_cu = 0, dev = 0, cus = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds) != hipSuccess) return 0;
@@ -1234,27 +1242,24 @@ static int resident_t() {
   return per_cu * cus;
 }
 
-int contract_resident_workgroups(bool mixed, int wm, int wn, int sc) {
-#define PS_SHAPE(a, b, c) \
-  if (wm == a && wn == b && sc == c) return mixed ? resident_t<float, a, b, c>() : resident_t<double, a, b, c>();
-  PS_SHAPE(4, 4, 1) PS_SHAPE(4, 4, 2) PS_SHAPE(2, 2, 1) PS_SHAPE(2, 2, 2)
-  PS_SHAPE(4, 2, 1) PS_SHAPE(4, 2, 2) PS_SHAPE(2, 4, 1) PS_SHAPE(2, 4, 2)
-  PS_SHAPE(4, 1, 1) PS_SHAPE(4, 1, 2) PS_SHAPE(4, 3, 1) PS_SHAPE(4, 3, 2)
-  PS_SHAPE(2, 1, 1) PS_SHAPE(2, 1, 2) PS_SHAPE(2, 3, 1) PS_SHAPE(2, 3, 2)
-  PS_SHAPE(1, 1, 1) PS_SHAPE(1, 1, 2) PS_SHAPE(1, 2, 1) PS_SHAPE(1, 2, 2)
-  PS_SHAPE(1, 3, 1) PS_SHAPE(1, 3, 2) PS_SHAPE(1, 4, 1) PS_SHAPE(1, 4, 2)
+int contract_resident_workgroups(bool mixed, int wm, int wn, int sc, int wr) {
+#define PS_SHAPE(a, b, c, d)                        \
+  if (wm == a && wn == b && sc == c && wr == d)     \
+    return mixed ? resident_t<float, a, b, c, d>() : resident_t<double, a, b, c, d>();
+  PS_SHAPES(PS_SHAPE)
 #undef PS_SHAPE
   return 0;
 }
+#undef PS_SHAPES
 
-hipError_t launch_contract_f64(int wm, int wn, int sc, const TaskDev* tasks, const TileDev* tiles, int ntiles,
-                               double* ws, hipStream_t st) {
-  return launch_contract_any<double>(wm, wn, sc, tasks, tiles, ntiles, ws, st);
+hipError_t launch_contract_f64(int wm, int wn, int sc, int wr, const TaskDev* tasks, const TileDev* tiles,
+                               int ntiles, double* ws, hipStream_t st) {
+  return launch_contract_any<double>(wm, wn, sc, wr, tasks, tiles, ntiles, ws, st);
 }
 
-hipError_t launch_contract_mixed(int wm, int wn, int sc, const TaskDev* tasks, const TileDev* tiles, int ntiles,
-                                 double* ws, hipStream_t st) {
-  return launch_contract_any<float>(wm, wn, sc, tasks, tiles, ntiles, ws, st);
+hipError_t launch_contract_mixed(int wm, int wn, int sc, int wr, const TaskDev* tasks, const TileDev* tiles,
+                                 int ntiles, double* ws, hipStream_t st) {
+  return launch_contract_any<float>(wm, wn, sc, wr, tasks, tiles, ntiles, ws, st);
 }
 
 hipError_t launch_reduce(const TaskDev* tasks, const RedDev* reds, const int32_t* items, int nitems,

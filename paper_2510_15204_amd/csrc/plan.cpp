@@ -1129,10 +1129,12 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       // groups 6 and 7: the 64 x 64 and 64 x 32 shapes in FP64, for the two-index tasks of a mixed job)
       // groups: 0 main shape, 1 the 64 x 64 shape, 2-4 the main shape narrowed to 32, 64, 96 columns,
       // 5 the 64 x 32 shape, 6-7 the FP64 64 x 64 and 64 x 32 shapes of a mixed job, 8-11 32-row
-      // shapes 32 x (32, 64, 96, 128) for the main shape's short row tiles
-      constexpr int NG = 12;
-      TileShape gshape[NG] = {shape, shape2, shape, shape, shape, shape2, shape2, shape2,
-                              shape, shape, shape, shape};
+      // shapes 32 x (32, 64, 96, 128) for short row tiles, 12-13 FP64 32 x (32, 64) for the short row
+      // tiles of a mixed job's FP64 tasks, 14-17 the 4 x 1 arrangement 128 x (16, 48, 80, 112) for
+      // last column tiles of an odd number of 16-column blocks
+      constexpr int NG = 18;
+      TileShape gshape[NG] = {shape, shape2, shape, shape, shape, shape2, shape2, shape2, shape,
+                              shape, shape, shape, shape2, shape2, shape, shape, shape, shape};
       for (int w = 1; w <= 3; ++w) {
         gshape[1 + w].wn = w;
         gshape[1 + w].slots = shape.slots_n[w];
@@ -1142,6 +1144,18 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
         gshape[7 + w].wn = w;
         gshape[7 + w].slots = shape.slots_short[w];
       }
+      for (int w = 1; w <= 2; ++w) {
+        gshape[11 + w].wm = 1;
+        gshape[11 + w].wn = w;
+        gshape[11 + w].slots = shape.slots_short_f64[w];
+      }
+      for (int k = 0; k < 4; ++k) {
+        gshape[14 + k].wm = 2;
+        gshape[14 + k].wn = 2 * k + 1;
+        gshape[14 + k].wr = 4;
+        gshape[14 + k].slots = shape.slots_tall[k];
+      }
+      const bool tall_ok = shape.wr == 2 && shape.bm() == 128;
       gshape[5].wn = 1;
       gshape[5].slots = shape.slots2n;
       gshape[6].slots = shape.slots2_f64;
@@ -1180,13 +1194,19 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
             int grp = grp0;
             const int w = (it.np + 31) / 32;
             if (grp0 == 0 && w < shape.wn) grp = 1 + w;
+            // a last column tile of an odd number of 16-column blocks (e.g. 37 columns: 48, not 64)
+            const int b16 = (it.np + 15) / 16;
+            if (grp0 == 0 && tall_ok && b16 % 2 == 1 && b16 < 2 * shape.wn) grp = 14 + b16 / 2;
             if (grp0 == 1 && w < shape2.wn) grp = 5;
             if (grp0 == 6 && w < shape2.wn) grp = 7;
             // a task's last row tile when it holds a quarter of the main shape's rows or fewer (e.g. 4
-            // of 128): a 32-row shape issues a quarter of the MFMAs
-            if (grp0 == 0 && shape.wm > 1 && w <= 4 && 4 * it.nrows <= shape.bm() &&
-                it.nu + it.nv <= gshape[7 + w].maxuv())
-              grp = 7 + w;
+            // of 128), or half of the 64-row shape's: a 32-row shape issues a quarter (a half) of the
+            // MFMAs
+            const int short_grp = grp0 == 6 ? 11 + w : 7 + w;
+            const bool short_rows = grp0 == 0 ? shape.wm > 1 && 4 * it.nrows <= shape.bm()
+                                              : 2 * it.nrows <= shape2.bm();
+            if (short_rows && w <= (grp0 == 6 ? 2 : 4) && it.nu + it.nv <= gshape[short_grp].maxuv())
+              grp = short_grp;
             total_cost[grp] += it.cost;
             items[grp].push_back(it);
           }
@@ -1197,11 +1217,11 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       ps.launches.clear();
       ps.tile0 = (int)p.tiles.size();
       int n_narrow = 0, n_second = 0;
-      for (int grp : {2, 3, 4, 5, 7, 8, 9, 10, 11}) n_narrow += items[grp].empty() ? 0 : 1;
+      for (int grp : {2, 3, 4, 5, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17}) n_narrow += items[grp].empty() ? 0 : 1;
       for (int grp : {1, 6}) n_second += items[grp].empty() ? 0 : 1;
       // launch order: main, narrow main, 32-row, 64 x 64, narrow 64 x 64, then the FP64 ones of a
       // mixed job
-      const int order[NG] = {0, 2, 3, 4, 8, 9, 10, 11, 1, 5, 6, 7};
+      const int order[NG] = {0, 2, 3, 4, 14, 15, 16, 17, 8, 9, 10, 11, 1, 5, 6, 7, 12, 13};
       for (int oi = 0; oi < NG; ++oi) {
         const int grp = order[oi];
         if (items[grp].empty()) continue;
@@ -1320,7 +1340,7 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
           p.reds.push_back(rd);
         }
         xcd_order(p.tiles, tg0, (int)p.tiles.size());
-        ps.launches.push_back({tg0, (int)p.tiles.size(), sh, grp == 6 || grp == 7});
+        ps.launches.push_back({tg0, (int)p.tiles.size(), sh, grp == 6 || grp == 7 || grp == 12 || grp == 13});
       }
       ps.tile1 = (int)p.tiles.size();
       ps.ws_elems = (size_t)ws;

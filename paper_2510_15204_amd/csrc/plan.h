@@ -15,6 +15,7 @@ namespace psint {
 // Contraction tile shape: 4 waves in a 2 x 2 arrangement, each wave WM x WN MFMA blocks of 16 x 16.
 struct TileShape {
   int wm = 4, wn = 4;
+  int wr = 2;                             // waves along the rows: 2 (2 x 2) or 4 (4 x 1)
   int sc = 1;                             // storage chunks (16 points each) per contraction stage
   int slots = 0;                          // work-groups of this shape resident on the device at once
                                           // (0 = unknown: no rounding of the K splits)
@@ -23,8 +24,10 @@ struct TileShape {
   int slots2n = 0;                        // the same for the 64 x 32 shape
   int slots2_f64 = 0, slots2n_f64 = 0;    // 64 x 64 and 64 x 32 in FP64 within a mixed job
   int slots_short[5] = {0, 0, 0, 0, 0};   // the 32-row shapes (wm = 1) of width wn = 1..4 (index wn)
-  int bm() const { return 32 * wm; }
-  int bn() const { return 32 * wn; }
+  int slots_short_f64[3] = {0, 0, 0};     // FP64 32 x 32 and 32 x 64 within a mixed job
+  int slots_tall[4] = {0, 0, 0, 0};       // the 4 x 1 shapes 128 x (16, 48, 80, 112) (index (wn - 1) / 2)
+  int bm() const { return 16 * wm * wr; }
+  int bn() const { return 16 * wn * (4 / wr); }
   int maxuv() const { return bm() + 4; }  // staged U + V columns per tile
   static constexpr int SC_MAX = 2;        // tiles start and end on multiples of this many chunks
 };

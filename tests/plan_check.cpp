@@ -70,6 +70,8 @@ int main(int argc, char** argv) {
   ts.slots = ts.slots2 = ts.slots2n = ts.slots2_f64 = ts.slots2n_f64 = slots;
   for (int w = 1; w < 4; ++w) ts.slots_n[w] = slots;
   for (int w = 1; w <= 4; ++w) ts.slots_short[w] = slots;
+  for (int w = 1; w <= 2; ++w) ts.slots_short_f64[w] = slots;
+  for (int k = 0; k < 4; ++k) ts.slots_tall[k] = slots;
   const size_t budget = (size_t)(atof(argv[4]) * 1e9);
   Plan p;
   std::string err;
@@ -121,10 +123,16 @@ int main(int argc, char** argv) {
     for (const auto& l : ps.launches)
       for (int i = l.tile0; i < l.tile1; ++i) {
         if (launch_of[i] >= 0) return fail("tile in two launches", i);
-        launch_of[i] = l.shape.wm * 10 + l.shape.wn;
+        launch_of[i] = l.shape.wm * 100 + l.shape.wn * 10 + l.shape.wr;
         const TileDev& t = p.tiles[i];
         if (t.nrows > l.shape.bm() || t.np > l.shape.bn()) return fail("tile larger than its shape", i);
         if (t.nu + t.nv > l.shape.maxuv()) return fail("staged columns beyond the shape", i);
+        // the launch's kernel reads its operands in the arrays' own element size: FP64 kernels for
+        // FP64 jobs and a mixed job's FP64 tasks, FP32 kernels for a mixed job's FP32 operands
+        const TaskHost& th = p.tasks[t.task];
+        const size_t es = job.precision == PS_PREC_MIXED && !l.f64 ? 4 : 8;
+        for (int a : {th.U, th.V, th.Y})
+          if (p.arrays[a].es != es) return fail("launch precision differs from its operands", i, a);
       }
   for (size_t i = 0; i < p.tiles.size(); ++i)
     if (launch_of[i] < 0) return fail("tile in no launch", (long)i);
