@@ -18,8 +18,9 @@
  *
  * Pins: closed forms, library routines and an independent 2-D quadrature fix every one- and
  * two-centre value and the three-centre values of collinear atoms.  Three-centre values with the
- * third centre off the pair axis have no closed form: they are pinned only through the point-charge
- * limit of (ab|P) and by grid self-convergence.
+ * third centre off the pair axis have no closed form: an independent 3-D integration (a fuzzy-cell
+ * partition of space with a spherical grid per atom) fixes them to the grid's own error, and the
+ * point-charge limit of (ab|P) fixes their leading behaviour.
  *
  * Units: bohr, hartree.  Functions are passed as rows (atom, n, l, m, zeta) of doubles.
  * All functions return 0 on success and a negative code on invalid input.

@@ -632,6 +632,57 @@ def test_point_charge_limit_of_three_centre_coulomb(natoms):
     assert 3.0 < rel[0] / rel[1] < 5.0
 
 
+def test_reference_integrator_closed_forms():
+    """The 3-D reference of the next test, pinned itself: a normalised 3d function integrates to 1;
+    <1s_A|1/r_C|1s_A> = 1/R - (zeta + 1/R) e^(-2 zeta R); an auxiliary 3d function's potential far away
+    is its multipole 4 pi/(2l+1) N (n+l+1)! zeta^-(n+l+2) Y_lm / r^(l+1)."""
+    import becke_reference as BR
+    xyz = TRI
+    p, w = BR.becke_grid(xyz, 80, 40, 80)
+    assert abs(np.sum(w * BR.sto((3, 2, -1, 0.8), xyz[1], p) ** 2) - 1) < 1e-12
+    z, R = 1.2, float(np.linalg.norm(xyz[2] - xyz[0]))
+    got = np.sum(w * BR.sto((1, 0, 0, z), xyz[0], p) ** 2 / np.linalg.norm(p - xyz[2], axis=1))
+    assert abs(got - (1 / R - (z + 1 / R) * math.exp(-2 * z * R))) < 2e-10
+    n, l, m, zeta = 3, 2, 1, 2.1
+    d = np.array([[0.3, -0.5, 0.7]])
+    d *= 45.0 / np.linalg.norm(d)
+    Nn = (2 * zeta) ** (n + 0.5) / math.sqrt(math.factorial(2 * n))
+    far = 4 * PI / (2 * l + 1) * Nn * math.factorial(n + l + 1) * zeta ** (-(n + l + 2)) \
+        * BR.real_ylm(l, m, d)[0] / 45.0 ** (l + 1)
+    assert abs(BR.sto_potential((n, l, m, zeta), np.zeros(3), d)[0] / far - 1) < 1e-12
+
+
+def test_generic_three_centre_values_vs_3d_reference():
+    """Generic three-centre values (Sections 2.2-2.3, eqs. 15-16): a bent triatomic in a rotated,
+    shifted frame (no symmetry plane along the functions' axes), s, p and d functions on A and B,
+    auxiliary s, p and d functions on C, and only C charged.  Every (ab|P) element and every V_ab
+    (the nucleus C summed on the refined G(A,B|C), or on one-centre grids) against the Becke-partitioned
+    3-D reference of tests/becke_reference.py (converged to 1e-10 or better).  The oracle's grid error:
+    (ab|P) 8e-8 on 24x24x12 cells and 8e-9 on 32x32x16; V 1.8e-6 and 8.6e-7 (the 1/r_C singularity at a
+    cell corner converges algebraically).  Both must fall with refinement.  Planted in a copy of the
+    oracle, an azimuth origin 0.3 rad off the third centre (no line through C) leaves V 8x further off
+    (6.9e-6) and fails; a misplaced function or contribution would be off by O(0.1)."""
+    import becke_reference as BR
+    from scipy.spatial.transform import Rotation
+    rot = Rotation.from_euler("zyx", [0.7, -0.4, 1.1]).as_matrix()
+    xyz = TRI @ rot.T + np.array([0.3, -0.2, 0.5])
+    basis = [[0, 1, 0, 0, 1.2], [0, 2, 1, 1, 1.0], [0, 3, 2, -2, 0.9], [1, 1, 0, 0, 1.1], [1, 2, 1, 0, 1.3]]
+    aux = [[2, 1, 0, 0, 2.0], [2, 2, 1, -1, 1.7], [2, 3, 2, 1, 2.1]]
+    p, w = BR.becke_grid(xyz, 80, 40, 80)
+    chi = np.array([BR.sto(f[1:], xyz[int(f[0])], p) for f in basis])
+    vp = np.array([BR.sto_potential(f[1:], xyz[int(f[0])], p) for f in aux])
+    cw = chi * w
+    ref_abP = np.einsum("ig,jg,pg->pij", cw, chi, vp)
+    ref_V = -np.einsum("ig,jg,g->ij", cw, chi, 1.0 / np.linalg.norm(p - xyz[2], axis=1))
+    assert np.abs(ref_abP).max() > 1.0 and np.abs(ref_V).max() > 0.3
+    err = []
+    for spec in (Spec(24, 24, 12, 4, 4), Spec(32, 32, 16, 4, 4)):
+        r = O.compute_full(MiniJob(xyz, [0.0, 0.0, 1.0], basis, aux, spec), want=("V", "abP"))
+        err.append((np.abs(r["abP"] - ref_abP).max(), np.abs(r["V"] - ref_V).max()))
+    assert err[1][0] < 2e-8 and err[1][1] < 2e-6, err
+    assert err[1][0] < 0.3 * err[0][0] and err[1][1] < 0.7 * err[0][1], err
+
+
 def test_grid_convergence_rmse_decreases():
     """RMSE (eq. 13) of S, T and (ab|P) against a larger grid shrinks along a grid ladder."""
     xyz = np.array([[0, 0, 0.8], [0, 0, -0.8]])
