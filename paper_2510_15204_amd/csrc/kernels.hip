@@ -183,15 +183,17 @@ __device__ __forceinline__ void inc_gamma_pair(int k_lo, int k_up, double x, dou
 }
 
 // ------------------------------------------------------------------------------------------------
-// Real solid harmonics of the unit displacement (x, y, z) at degree l from degrees l - 1 (Cm1, Sm1)
-// and l - 2 (Cm2, Sm2) into C, Sv (the recurrences below).
+// Real solid harmonics of the unit displacement (x, y, z) at degree l from degree l - 1 (Cm1, Sm1),
+// written over degree l - 2 in (C, Sv): entry m of degree l needs entry m of degree l - 2 and entries
+// m, m - 1 of degree l - 1 only (the recurrences below), so two register sets alternate by the
+// parity of l.
 // ------------------------------------------------------------------------------------------------
-__device__ __forceinline__ void harmonic_level(int l, double x, double y, double z, const double* Cm2,
-                                               const double* Sm2, const double* Cm1, const double* Sm1,
-                                               double* C, double* Sv) {
+__device__ __forceinline__ void harmonic_level(int l, double x, double y, double z, const double* Cm1,
+                                               const double* Sm1, double* C, double* Sv) {
   if (l == 0) {
+#pragma unroll
+    for (int m = 0; m <= LMAX; ++m) C[m] = Sv[m] = 0.0;
     C[0] = 1.0;
-    Sv[0] = 0.0;
     return;
   }
   const double tl = 2.0 * l - 1.0;
@@ -208,8 +210,8 @@ __device__ __forceinline__ void harmonic_level(int l, double x, double y, double
       sn = tl * z * Sm1[m];
     } else if (m < l - 1) {
       const double inv = kInv.v[l - m];
-      cn = (tl * z * Cm1[m] - (l + m - 1.0) * Cm2[m]) * inv;
-      sn = (tl * z * Sm1[m] - (l + m - 1.0) * Sm2[m]) * inv;
+      cn = (tl * z * Cm1[m] - (l + m - 1.0) * C[m]) * inv;
+      sn = (tl * z * Sm1[m] - (l + m - 1.0) * Sv[m]) * inv;
     }
     C[m] = cn;
     Sv[m] = sn;
@@ -316,15 +318,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void e
   const double dz = cen == 0 ? geo.d[0][2] : (cen == 1 ? geo.d[1][2] : geo.d[2][2]);
   const double ir = 1.0 / r;
   const double x = dx * ir, y = dy * ir, z = dz * ir;
-  double Cm2[LMAX + 1], Sm2[LMAX + 1], Cm1[LMAX + 1], Sm1[LMAX + 1], C[LMAX + 1], Sv[LMAX + 1];
+  // harmonics of even degrees in (Pc, Ps), odd degrees in (Qc, Qs)
+  double Pc[LMAX + 1], Ps[LMAX + 1], Qc[LMAX + 1], Qs[LMAX + 1];
 #pragma unroll
-  for (int m = 0; m <= LMAX; ++m) Cm2[m] = Sm2[m] = Cm1[m] = Sm1[m] = C[m] = Sv[m] = 0.0;
+  for (int m = 0; m <= LMAX; ++m) Pc[m] = Ps[m] = Qc[m] = Qs[m] = 0.0;
   int lmax_seg = 0;
   for (int l = 0; l <= LMAX; ++l)
     if (S.l_off[l + 1] > S.l_off[l]) lmax_seg = l;
-  for (int l = 0; l <= lmax_seg; ++l) {
-    harmonic_level(l, x, y, z, Cm2, Sm2, Cm1, Sm1, C, Sv);
-    // shells with this l
+  // the shells of degree l, whose harmonics are (C, Sv)
+  auto shells_of = [&](int l, const double* C, const double* Sv) __attribute__((always_inline)) {
     for (int s = S.l_off[l]; s < S.l_off[l + 1]; ++s) {
       const ShellDev sh = shells[s];
       const double ex = exp(-sh.zeta * r);
@@ -369,13 +371,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void e
         }
       }
     }
-#pragma unroll
-    for (int m = 0; m <= LMAX; ++m) {
-      Cm2[m] = Cm1[m];
-      Sm2[m] = Sm1[m];
-      Cm1[m] = C[m];
-      Sm1[m] = Sv[m];
-    }
+  };
+  for (int l = 0; l <= lmax_seg; l += 2) {
+    harmonic_level(l, x, y, z, Qc, Qs, Pc, Ps);
+    shells_of(l, Pc, Ps);
+    if (l + 1 > lmax_seg) break;
+    harmonic_level(l + 1, x, y, z, Pc, Ps, Qc, Qs);
+    shells_of(l + 1, Qc, Qs);
   }
 }
 
@@ -462,21 +464,16 @@ __global__ __launch_bounds__(256) void eval_shared_kernel(const ShareSegDev* __r
         const double dy = lx * G.ex[1] + ly * G.ey[1] + lz * G.ez[1];
         const double dz = lx * G.ex[2] + ly * G.ey[2] + lz * G.ez[2];
         const double x = dx * ir_, y = dy * ir_, z = dz * ir_;
-        double Cm2[LMAX + 1], Sm2[LMAX + 1], Cm1[LMAX + 1], Sm1[LMAX + 1], C[LMAX + 1], Sv[LMAX + 1];
+        // even degrees in (Pc, Ps), odd degrees in (Qc, Qs); degree l ends in the set of its parity
+        double Pc[LMAX + 1], Ps[LMAX + 1], Qc[LMAX + 1], Qs[LMAX + 1];
 #pragma unroll
-        for (int mm = 0; mm <= LMAX; ++mm) Cm2[mm] = Sm2[mm] = Cm1[mm] = Sm1[mm] = C[mm] = Sv[mm] = 0.0;
-        for (int ll = 0; ll <= l; ++ll) {
-          harmonic_level(ll, x, y, z, Cm2, Sm2, Cm1, Sm1, C, Sv);
-          if (ll < l) {
-#pragma unroll
-            for (int mm = 0; mm <= LMAX; ++mm) {
-              Cm2[mm] = Cm1[mm];
-              Sm2[mm] = Sm1[mm];
-              Cm1[mm] = C[mm];
-              Sm1[mm] = Sv[mm];
-            }
-          }
+        for (int mm = 0; mm <= LMAX; ++mm) Pc[mm] = Ps[mm] = Qc[mm] = Qs[mm] = 0.0;
+        for (int ll = 0; ll <= l; ll += 2) {
+          harmonic_level(ll, x, y, z, Qc, Qs, Pc, Ps);
+          if (ll + 1 > l) break;
+          harmonic_level(ll + 1, x, y, z, Pc, Ps, Qc, Qs);
         }
+        const bool odd = (l & 1) != 0;
         GT* __restrict__ w0 = (GT*)mem[c].arr0 + gw * S.nf;
         GD* __restrict__ d0 = (GD*)mem[c].arr0d + gw * S.nf;
         const bool has0 = mem[c].arr0 != nullptr, has0d = sizeof(T) == 4 && mem[c].arr0d != nullptr;
@@ -490,12 +487,12 @@ __global__ __launch_bounds__(256) void eval_shared_kernel(const ShareSegDev* __r
             if (mm > l) break;
             const MEntry ep = me0[mm], en = me0[-mm];
             if (ep.col >= 0) {
-              const double v = rad[u] * (C[mm] * ep.f);
+              const double v = rad[u] * ((odd ? Qc[mm] : Pc[mm]) * ep.f);
               if (has0) w0[(int64_t)ep.col * KC + loff] = (T)v;
               if (has0d) d0[(int64_t)ep.col * KC + loff] = v;
             }
             if (mm > 0 && en.col >= 0) {
-              const double v = rad[u] * (Sv[mm] * en.f);
+              const double v = rad[u] * ((odd ? Qs[mm] : Ps[mm]) * en.f);
               if (has0) w0[(int64_t)en.col * KC + loff] = (T)v;
               if (has0d) d0[(int64_t)en.col * KC + loff] = v;
             }
