@@ -218,7 +218,16 @@ int main(int argc, char** argv) {
   for (size_t si = 0; si < p.segs.size(); ++si)
     if ((p.segs[si].dev.skip != 0) != (skipped_by[si] == 1)) return fail("segment skips without one share", (long)si);
   if (share && kept == 0) return fail("no share kept");
-  printf("ok %zu tiles %zu items %zu passes %zu shares%s\n", p.tiles.size(), p.reds.size(), p.passes.size(), kept,
-         p.overlap ? " overlapped" : "");
+  std::map<std::string, int> shapes;  // launch shapes used, as wm.wn.sc.wr
+  for (const Pass& ps : p.passes)
+    for (const auto& l : ps.launches) {
+      char key[32];
+      snprintf(key, sizeof key, "%d.%d.%d.%d", l.shape.wm, l.shape.wn, l.shape.sc, l.shape.wr);
+      shapes[key]++;
+    }
+  printf("ok %zu tiles %zu items %zu passes %zu shares%s shapes", p.tiles.size(), p.reds.size(), p.passes.size(),
+         kept, p.overlap ? " overlapped" : "");
+  for (const auto& kv : shapes) printf(" %s", kv.first.c_str());
+  printf("\n");
   return 0;
 }

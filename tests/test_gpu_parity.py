@@ -14,6 +14,7 @@ import oracle as O
 from conftest import MiniJob, Spec
 from paper_2510_15204_amd import psint
 from paper_2510_15204_amd import workloads as W
+import tile_shape_jobs as TS
 
 pytestmark = pytest.mark.gpu
 
@@ -283,6 +284,26 @@ def test_invalid_inputs_rejected(ctx, bad):
     with pytest.raises(psint.PsError) as e:
         ctx.compute(job)
     assert e.value.status == expect
+
+
+@pytest.mark.parametrize("n_aux", sorted(TS.TALL_CASES))
+def test_tall_and_short_row_tiles_match_oracle(ctx, n_aux):
+    """Jobs whose plans use the 4 x 1 wave arrangement (128 rows x 16, 48, 80 or 112 columns, one per
+    case), the 128-row shape and the 32-row shapes for short row tiles (tests/tile_shape_jobs.py; the
+    CPU plan test checks that they do): FP64 against the oracle at 1e-10, mixed with (ab|P) within
+    1e-7 of its largest element and the FP64 two-index outputs at 1e-10.  The factor of (P|Q) is not
+    asked for: the larger auxiliary sets make the metric ill-conditioned (smallest to largest
+    eigenvalue down to 1e-13), which is not what these jobs test."""
+    job = TS.tall_job(n_aux)
+    outs = ("S", "T", "V", "PQ", "abP")
+    ref = O.compute_full(job, want=outs)
+    got, _, rc = ctx.compute(job, outputs=outs)
+    assert rc == psint.PS_OK
+    _compare(got, ref, TOL64, f"tall shapes, {n_aux} auxiliaries on C")
+    mix, _, _ = ctx.compute(job, outputs=outs, precision="mixed")
+    for k in ("S", "T", "V", "PQ", "abP"):
+        tol = 1e-7 * float(np.max(np.abs(ref[k]))) if k == "abP" else TOL64
+        assert np.max(np.abs(mix[k] - ref[k])) <= tol, (n_aux, k)
 
 
 @pytest.mark.parametrize("ksplit", [1, 3, 17])

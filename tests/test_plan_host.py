@@ -11,6 +11,7 @@ import subprocess
 import pytest
 
 from paper_2510_15204_amd import workloads as W
+import tile_shape_jobs as TS
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -26,7 +27,7 @@ def checker(tmp_path_factory):
 
 
 def _write_job(job, path):
-    lines = [str(job.n_atoms)]
+    lines = [str(len(job.xyz))]
     lines += [" ".join(repr(float(v)) for v in (*x, z)) for x, z in zip(job.xyz, job.Z)]
     for fns in (job.basis, job.aux):
         lines.append(str(len(fns)))
@@ -63,3 +64,16 @@ def test_plan_invariants(checker, name, prec, budget_gb, share):
     assert out.returncode == 0 and out.stdout.startswith("ok"), out.stdout + out.stderr
     if "overlap" in share:
         assert ("overlapped" in out.stdout) == (budget_gb < 200.0 or name == "hydrocarbon9"), out.stdout
+
+
+@pytest.mark.parametrize("n_aux", sorted(TS.TALL_CASES))
+def test_tall_and_short_row_shapes_are_planned(checker, n_aux):
+    """The GPU parity jobs of tests/tile_shape_jobs.py keep exercising what they are for: the 128-row
+    shape, the tall last-column shape of their auxiliary count and a 32-row short row tile."""
+    exe, d = checker
+    f = d / f"tall_{n_aux}.txt"
+    _write_job(TS.tall_job(n_aux), f)
+    out = subprocess.run([exe, str(f), "0", "512", "200"], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0 and out.stdout.startswith("ok"), out.stdout
+    shapes = out.stdout.split("shapes")[1].split()
+    assert TS.TALL_CASES[n_aux] in shapes and any(s.startswith("1.") for s in shapes), shapes
