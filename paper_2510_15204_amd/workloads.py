@@ -234,10 +234,16 @@ def hydrocarbon_geometry(rng, cc=2.9, ch=2.05, jitter=0.05):
 
 
 def hydrocarbon9(points_choices=(64, 80, 96, 112, 128)) -> Job:
-    """9-atom C3H6-shaped molecule, C 55 / H 30 functions, aux 3x, 36 pair grids of 64..128 points/axis."""
+    """9-atom C3H6-shaped molecule, C 55 / H 30 functions, aux 3x, 36 pair grids of 64..128 points/axis.
+
+    Auxiliary exponents span 4x the element's basis range at both ends: with the lower end at 2x, the
+    most diffuse auxiliary functions of neighbouring atoms (2-3 bohr apart) are so nearly dependent in
+    the Coulomb metric that the grids' quadrature error leaves (P|Q) indefinite (smallest eigenvalue
+    -5e-6 of 870); from 4x up it is positive definite (smallest eigenvalue 6e-9 of 190)."""
     rng = rng_for(3)
     xyz, Z = hydrocarbon_geometry(rng)
-    basis, aux = build_basis(rng, Z.astype(int), "QZ", "auxQZ", n_max=4)
+    aux_ranges = {int(z): (4 * ZETA_RANGE[int(z)][0], 4 * ZETA_RANGE[int(z)][1]) for z in set(Z.astype(int).tolist())}
+    basis, aux = build_basis(rng, Z.astype(int), "QZ", "auxQZ", n_max=4, aux_ranges=aux_ranges)
     pair_grids = {}
     n = len(Z)
     for a in range(n):
