@@ -1219,8 +1219,8 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
       int n_narrow = 0, n_second = 0;
       for (int grp : {2, 3, 4, 5, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17}) n_narrow += items[grp].empty() ? 0 : 1;
       for (int grp : {1, 6}) n_second += items[grp].empty() ? 0 : 1;
-      // launch order: main, narrow main, 32-row, 64 x 64, narrow 64 x 64, then the FP64 ones of a
-      // mixed job
+      // launch order: main, narrow main, tall, 32-row, 64 x 64, narrow 64 x 64, then the FP64 ones of
+      // a mixed job (64 x 64, 64 x 32, 32-row)
       const int order[NG] = {0, 2, 3, 4, 14, 15, 16, 17, 8, 9, 10, 11, 1, 5, 6, 7, 12, 13};
       for (int oi = 0; oi < NG; ++oi) {
         const int grp = order[oi];
