@@ -16,6 +16,7 @@
 //                    register operands), for reading roofline fractions.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <type_traits>
 
@@ -848,6 +849,45 @@ __global__ __launch_bounds__(256, 1) void contract_f64(const TaskDev* __restrict
   contract_body<double, WM, WN, SC, WR>(tasks[t.task], t, (__attribute__((address_space(3))) double*)smem_d, ws);
 }
 
+// The 128-row shapes of a pass in one launch: each tile runs the body of the shape it names
+// (kMergedShapes).  The kernel's registers and LDS are those of its largest shape (128 x 128), which
+// the other shapes of this family need as well to within a few percent; one launch instead of up to
+// eight drains the device once per pass.
+template <typename T, int SC>
+__device__ __forceinline__ void contract_merged_body(const TaskDev* __restrict__ tasks, const TileDev& t,
+                                                     __attribute__((address_space(3))) T* lds,
+                                                     double* __restrict__ ws) {
+  constexpr auto& M = kMergedShapes;
+  const TaskDev& Tk = tasks[t.task];
+  switch (t.shape) {
+    case 0: contract_body<T, M[0][0], M[0][1], SC, M[0][2]>(Tk, t, lds, ws); break;
+    case 1: contract_body<T, M[1][0], M[1][1], SC, M[1][2]>(Tk, t, lds, ws); break;
+    case 2: contract_body<T, M[2][0], M[2][1], SC, M[2][2]>(Tk, t, lds, ws); break;
+    case 3: contract_body<T, M[3][0], M[3][1], SC, M[3][2]>(Tk, t, lds, ws); break;
+    case 4: contract_body<T, M[4][0], M[4][1], SC, M[4][2]>(Tk, t, lds, ws); break;
+    case 5: contract_body<T, M[5][0], M[5][1], SC, M[5][2]>(Tk, t, lds, ws); break;
+    case 6: contract_body<T, M[6][0], M[6][1], SC, M[6][2]>(Tk, t, lds, ws); break;
+    default: contract_body<T, M[7][0], M[7][1], SC, M[7][2]>(Tk, t, lds, ws); break;
+  }
+}
+
+template <int SC>
+__global__ __launch_bounds__(256, 1) void contract_f64_merged(const TaskDev* __restrict__ tasks,
+                                                              const TileDev* __restrict__ tiles,
+                                                              double* __restrict__ ws) {
+  extern __shared__ __attribute__((aligned(16))) double smem_md[];
+  const TileDev t = tiles[blockIdx.x];
+  contract_merged_body<double, SC>(tasks, t, (__attribute__((address_space(3))) double*)smem_md, ws);
+}
+
+template <int SC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void contract_mixed_merged(
+    const TaskDev* __restrict__ tasks, const TileDev* __restrict__ tiles, double* __restrict__ ws) {
+  extern __shared__ __attribute__((aligned(16))) float smem_mf[];
+  const TileDev t = tiles[blockIdx.x];
+  contract_merged_body<float, SC>(tasks, t, (__attribute__((address_space(3))) float*)smem_mf, ws);
+}
+
 // Two waves per SIMD asked of the compiler: the widest FP32 tile then keeps its FP64 accumulators
 // and operands in VGPRs rather than splitting them into AGPRs (measured 2% faster than leaving the
 // allocation free).
@@ -1213,10 +1253,38 @@ static hipError_t launch_contract_t(const TaskDev* tasks, const TileDev* tiles, 
   X(1, 3, 2, 2) X(1, 4, 1, 2) X(1, 4, 2, 2) X(2, 1, 1, 4) X(2, 1, 2, 4) X(2, 3, 1, 4) X(2, 3, 2, 4) \
   X(2, 5, 1, 4) X(2, 5, 2, 4) X(2, 7, 1, 4) X(2, 7, 2, 4)
 
+// A merged launch (wm == 0): LDS of its largest shape.
+template <typename T, int SC, int I>
+constexpr int merged_lds() {
+  return ContractCfg<T, kMergedShapes[I][0], kMergedShapes[I][1], SC, kMergedShapes[I][2]>::LDS_BYTES;
+}
+
+template <typename T, int SC>
+static hipError_t launch_merged_t(const TaskDev* tasks, const TileDev* tiles, int ntiles, double* ws,
+                                  hipStream_t st) {
+  constexpr int lds = std::max({merged_lds<T, SC, 0>(), merged_lds<T, SC, 1>(), merged_lds<T, SC, 2>(),
+                                merged_lds<T, SC, 3>(), merged_lds<T, SC, 4>(), merged_lds<T, SC, 5>(),
+                                merged_lds<T, SC, 6>(), merged_lds<T, SC, 7>()});
+  static_assert(lds <= 160 * 1024, "LDS budget");
+  const void* fn = sizeof(T) == 8 ? (const void*)contract_f64_merged<SC> : (const void*)contract_mixed_merged<SC>;
+  static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (attr != hipSuccess) return attr;
+  if constexpr (sizeof(T) == 8)
+    hipLaunchKernelGGL((contract_f64_merged<SC>), dim3(ntiles), dim3(256), lds, st, tasks, tiles, ws);
+  else
+    hipLaunchKernelGGL((contract_mixed_merged<SC>), dim3(ntiles), dim3(256), lds, st, tasks, tiles, ws);
+  return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t launch_contract_any(int wm, int wn, int sc, int wr, const TaskDev* tasks, const TileDev* tiles,
                                       int ntiles, double* ws, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
+  if (wm == 0) {
+    if (sc == 1) return launch_merged_t<T, 1>(tasks, tiles, ntiles, ws, st);
+    if (sc == 2) return launch_merged_t<T, 2>(tasks, tiles, ntiles, ws, st);
+    return hipErrorInvalidValue;
+  }
 #define PS_SHAPE(a, b, c, d) \
   if (wm == a && wn == b && sc == c && wr == d) return launch_contract_t<T, a, b, c, d>(tasks, tiles, ntiles, ws, st);
   PS_SHAPES(PS_SHAPE)

@@ -318,6 +318,13 @@ int32_t build_grid(const ps_atom* atoms, int n_atoms, int A, int B, int C, const
 // on one XCD's queue and its members get consecutive slots there, so they run together and share
 // the Y columns in that XCD's L2.  Groups go to the least-loaded queue; the queues are then
 // interleaved into blockIdx order.
+// A tile's length in MFMA steps: its chunks times the MFMA blocks per wave of its shape (tiles of one
+// single-shape launch all weigh 16 per chunk, so only their chunk counts order them).
+static double tile_weight(const TileDev& t) {
+  const int* m = kMergedShapes[t.shape & 7];
+  return (double)t.nkc * m[0] * m[1];
+}
+
 static void xcd_order(std::vector<TileDev>& tiles, int t0, int t1) {
   constexpr int NX = 8;
   if (t1 - t0 <= NX) return;
@@ -337,7 +344,7 @@ static void xcd_order(std::vector<TileDev>& tiles, int t0, int t1) {
   // longest groups first (a group's tiles share one K range, so one length): each queue then runs
   // its longest tiles first and the short ones fill the end of the launch
   std::stable_sort(order_keys.begin(), order_keys.end(), [&](const auto& a, const auto& b) {
-    return tiles[groups[a][0]].nkc > tiles[groups[b][0]].nkc;
+    return tile_weight(tiles[groups[a][0]]) > tile_weight(tiles[groups[b][0]]);
   });
   std::vector<std::vector<int>> q(NX);
   std::vector<double> load(NX, 0.0);
@@ -348,7 +355,7 @@ static void xcd_order(std::vector<TileDev>& tiles, int t0, int t1) {
       if (load[x] < load[best]) best = x;
     for (int i : g) {
       q[best].push_back(i);
-      load[best] += (double)tiles[i].nkc;
+      load[best] += tile_weight(tiles[i]);
     }
   }
   std::vector<TileDev> out;
@@ -1341,6 +1348,36 @@ int32_t build_plan(const ps_job* job, const TileShape& shape, int ksplit_overrid
         }
         xcd_order(p.tiles, tg0, (int)p.tiles.size());
         ps.launches.push_back({tg0, (int)p.tiles.size(), sh, grp == 6 || grp == 7 || grp == 12 || grp == 13});
+      }
+      // The 128-row launches (the main shape, its narrowed and tall last-column shapes; consecutive,
+      // first in the launch order, one precision) become one launch whose tiles name their shapes:
+      // one drain of the device per pass instead of one per shape.  Its tiles are ordered again,
+      // longest first by MFMA steps, across all of them.
+      {
+        auto merged_id = [](const TileShape& s) {
+          for (int k = 0; k < 8; ++k)
+            if (s.wm == kMergedShapes[k][0] && s.wn == kMergedShapes[k][1] && s.wr == kMergedShapes[k][2]) return k;
+          return -1;
+        };
+        std::vector<Pass::Launch> kept;
+        int m0 = -1, m1 = -1;
+        for (const auto& l : ps.launches) {
+          const int id = merged_id(l.shape);
+          if (id >= 0 && !l.f64 && l.shape.sc == shape.sc && (m1 < 0 || l.tile0 == m1)) {
+            for (int i = l.tile0; i < l.tile1; ++i) p.tiles[i].shape = id;
+            if (m0 < 0) m0 = l.tile0;
+            m1 = l.tile1;
+          } else {
+            kept.push_back(l);
+          }
+        }
+        if (m0 >= 0) {
+          xcd_order(p.tiles, m0, m1);
+          TileShape merged = shape;
+          merged.wm = 0;  // marks the merged launch
+          kept.insert(kept.begin(), Pass::Launch{m0, m1, merged, false});
+        }
+        ps.launches = kept;
       }
       ps.tile1 = (int)p.tiles.size();
       ps.ws_elems = (size_t)ws;

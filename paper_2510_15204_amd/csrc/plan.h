@@ -85,7 +85,7 @@ struct Pass {
   int64_t shared_blocks = 0;    // blocks of their launch
   struct Launch {
     int tile0, tile1;   // consecutive tiles of one contraction launch
-    TileShape shape;
+    TileShape shape;    // wm == 0: the merged launch of the 128-row shapes (TileDev::shape per tile)
     bool f64 = false;   // FP64 contraction within a mixed job (its two-index tasks)
   };
   std::vector<Launch> launches;  // main shape, 64 x 64 shape, then narrow last-column-tile shapes

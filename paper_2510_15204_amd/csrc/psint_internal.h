@@ -131,6 +131,12 @@ struct TaskDev {
   int32_t pad0;
 };
 
+// The 128-row tile shapes that share one merged contraction launch per memory pass, as (WM, WN, WR):
+// the 2 x 2-wave shapes 128 x 128, 96, 64, 32 and the 4 x 1-wave (tall) shapes 128 x 16, 48, 80, 112.
+// A tile of a merged launch names its shape by its index here (TileDev::shape).
+constexpr int kMergedShapes[8][3] = {{4, 4, 2}, {4, 3, 2}, {4, 2, 2}, {4, 1, 2},
+                                     {2, 1, 4}, {2, 3, 4}, {2, 5, 4}, {2, 7, 4}};
+
 // One work-group's share: a (pair-rows x y-columns) tile of a task over a range of point chunks.
 struct TileDev {
   int32_t task;
@@ -138,7 +144,7 @@ struct TileDev {
   int32_t ulo, nu;       // U columns staged
   int32_t vlo, nv;       // V columns staged
   int32_t p0, np;        // y columns [y0 + p0, y0 + p0 + np)
-  int32_t pad0;
+  int32_t shape;         // index into kMergedShapes in a merged launch; 0 in a single-shape launch
   int64_t kc0, nkc;      // chunk range
   int64_t ws;            // workspace offset (elements) of the BM x BN partial tile
 };

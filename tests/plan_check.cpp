@@ -123,10 +123,19 @@ int main(int argc, char** argv) {
     for (const auto& l : ps.launches)
       for (int i = l.tile0; i < l.tile1; ++i) {
         if (launch_of[i] >= 0) return fail("tile in two launches", i);
-        launch_of[i] = l.shape.wm * 100 + l.shape.wn * 10 + l.shape.wr;
+        launch_of[i] = 1 + (int)(&l - ps.launches.data());
         const TileDev& t = p.tiles[i];
-        if (t.nrows > l.shape.bm() || t.np > l.shape.bn()) return fail("tile larger than its shape", i);
-        if (t.nu + t.nv > l.shape.maxuv()) return fail("staged columns beyond the shape", i);
+        TileShape ts2 = l.shape;  // a merged launch: the shape the tile names
+        if (l.shape.wm == 0) {
+          if (t.shape < 0 || t.shape > 7) return fail("merged tile without a shape", i);
+          ts2.wm = kMergedShapes[t.shape][0];
+          ts2.wn = kMergedShapes[t.shape][1];
+          ts2.wr = kMergedShapes[t.shape][2];
+        } else if (t.shape != 0) {
+          return fail("shape named outside a merged launch", i);
+        }
+        if (t.nrows > ts2.bm() || t.np > ts2.bn()) return fail("tile larger than its shape", i);
+        if (t.nu + t.nv > ts2.maxuv()) return fail("staged columns beyond the shape", i);
         // the launch's kernel reads its operands in the arrays' own element size: FP64 kernels for
         // FP64 jobs and a mixed job's FP64 tasks, FP32 kernels for a mixed job's FP32 operands
         const TaskHost& th = p.tasks[t.task];
@@ -218,12 +227,21 @@ int main(int argc, char** argv) {
   for (size_t si = 0; si < p.segs.size(); ++si)
     if ((p.segs[si].dev.skip != 0) != (skipped_by[si] == 1)) return fail("segment skips without one share", (long)si);
   if (share && kept == 0) return fail("no share kept");
-  std::map<std::string, int> shapes;  // launch shapes used, as wm.wn.sc.wr
+  std::map<std::string, int> shapes;  // tile shapes used, as wm.wn.sc.wr ("merged" if a launch merges them)
   for (const Pass& ps : p.passes)
     for (const auto& l : ps.launches) {
       char key[32];
-      snprintf(key, sizeof key, "%d.%d.%d.%d", l.shape.wm, l.shape.wn, l.shape.sc, l.shape.wr);
-      shapes[key]++;
+      if (l.shape.wm == 0) {
+        shapes["merged"]++;
+        for (int i = l.tile0; i < l.tile1; ++i) {
+          const int* m = kMergedShapes[p.tiles[i].shape];
+          snprintf(key, sizeof key, "%d.%d.%d.%d", m[0], m[1], l.shape.sc, m[2]);
+          shapes[key]++;
+        }
+      } else {
+        snprintf(key, sizeof key, "%d.%d.%d.%d", l.shape.wm, l.shape.wn, l.shape.sc, l.shape.wr);
+        shapes[key]++;
+      }
     }
   printf("ok %zu tiles %zu items %zu passes %zu shares%s shapes", p.tiles.size(), p.reds.size(), p.passes.size(),
          kept, p.overlap ? " overlapped" : "");

@@ -77,3 +77,4 @@ def test_tall_and_short_row_shapes_are_planned(checker, n_aux):
     assert out.returncode == 0 and out.stdout.startswith("ok"), out.stdout
     shapes = out.stdout.split("shapes")[1].split()
     assert TS.TALL_CASES[n_aux] in shapes and any(s.startswith("1.") for s in shapes), shapes
+    assert "merged" in shapes, shapes  # the 128-row shapes share one launch
