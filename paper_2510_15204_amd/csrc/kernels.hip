@@ -850,9 +850,10 @@ __global__ __launch_bounds__(256, 1) void contract_f64(const TaskDev* __restrict
 }
 
 // The 128-row shapes of a pass in one launch: each tile runs the body of the shape it names
-// (kMergedShapes).  The kernel's registers and LDS are those of its largest shape (128 x 128), which
-// the other shapes of this family need as well to within a few percent; one launch instead of up to
-// eight drains the device once per pass.
+// (kMergedShapes).  The kernel's registers and LDS are those of its largest shape (128 x 128): two
+// work-groups per CU, which the LDS of every other shape of this family allows on its own too, except
+// the two narrowest (128 x 32 and the tall 128 x 16, three).  One launch instead of up to eight drains
+// the device once per pass.
 template <typename T, int SC>
 __device__ __forceinline__ void contract_merged_body(const TaskDev* __restrict__ tasks, const TileDev& t,
                                                      __attribute__((address_space(3))) T* lds,
