@@ -306,6 +306,29 @@ def test_tall_and_short_row_tiles_match_oracle(ctx, n_aux):
         assert np.max(np.abs(mix[k] - ref[k])) <= tol, (n_aux, k)
 
 
+@pytest.mark.parametrize("tiling", [(4, 4, 2), (4, 4, 1), (4, 2, 1), (2, 4, 2)])
+def test_explicit_tilings_match_oracle(tiling):
+    """Non-default tilings (ps_set_tiling) on a job with 128-row, tall and short row tiles: the merged
+    launch of the 128-row shapes with the other stage size in each precision (FP64 32-point stages,
+    FP32 16-point stages), a narrower main shape, and a 64-row main shape (no merged launch); FP64
+    against the oracle at 1e-10, mixed with (ab|P) within 1e-7 of its largest element."""
+    job = TS.tall_job(138)
+    outs = ("S", "T", "V", "PQ", "abP")
+    ref = O.compute_full(job, want=outs)
+    c = psint.Context(0)
+    try:
+        c.set_tiling(*tiling, 0)
+        got, _, rc = c.compute(job, outputs=outs)
+        assert rc == psint.PS_OK
+        _compare(got, ref, TOL64, f"tiling {tiling}")
+        mix, _, _ = c.compute(job, outputs=outs, precision="mixed")
+    finally:
+        c.close()
+    for k in outs:
+        tol = 1e-7 * float(np.max(np.abs(ref[k]))) if k == "abP" else TOL64
+        assert np.max(np.abs(mix[k] - ref[k])) <= tol, (tiling, k)
+
+
 @pytest.mark.parametrize("ksplit", [1, 3, 17])
 def test_explicit_k_splits_match_oracle(ksplit):
     """The same job with every contraction item split into 1, 3 or 17 point ranges (partial tiles
