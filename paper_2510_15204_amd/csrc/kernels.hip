@@ -507,11 +507,11 @@ __global__ __launch_bounds__(256) void eval_shared_kernel(const ShareSegDev* __r
 // ------------------------------------------------------------------------------------------------
 // Contraction kernels.  256 threads = 4 waves, WR along the rows and 4 / WR along the columns (2 x 2,
 // or 4 x 1 for tiles whose width is an odd number of 16-column blocks); wave (wm, wn) owns WM x WN
-// MFMA blocks of 16 x 16.  Points are consumed in stages of SC storage chunks (SC * 16 points).  Each stage's U, V
-// and Y columns sit in LDS as rows of SC * 16 values padded by 4 (bank-conflict-free operand reads);
-// two LDS buffers alternate, so one barrier per stage suffices: while the MFMAs of stage s run on one
-// buffer, the registers holding stage s+1 (loaded during stage s-1) are written to the other buffer
-// and the loads of stage s+2 are issued, interleaved between the MFMA steps.
+// MFMA blocks of 16 x 16.  Points are consumed in stages of SC storage chunks (SC * 16 points).  Each
+// stage's U, V and Y columns sit in LDS as padded rows of SC * 16 values (bank-conflict-free operand
+// reads); two LDS buffers alternate, so one barrier per stage suffices: while the MFMAs of stage s run
+// on one buffer, direct global->LDS copies fill the other with stage s+1, issued between the MFMA
+// steps.
 //
 // Operand layouts (probed on gfx950): A lane l = A[l%16][l/16], B lane l = B[l/16][l%16];
 // v_mfma_f64_16x16x4 result register r of lane l = D[4r + l/16][l%16];
@@ -543,6 +543,9 @@ struct ContractCfg {
 // rows [0, nu+nv) or the Y rows [MAXUV, MAXUV+np).  Each thread's source offset for every copy it
 // issues is computed once per tile; per stage only the chunk base moves.  The copies of stage s+1
 // are spread between the MFMA steps of stage s so their address work hides under the matrix pipe.
+// Instruction classes of __builtin_amdgcn_sched_group_barrier (LLVM AMDGPU scheduling groups).
+constexpr int SG_VALU = 0x002, SG_MFMA = 0x008, SG_DSR = 0x100;
+
 template <typename T, int WM, int WN, int SC_, int WR>
 __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, const TileDev& t,
                                               __attribute__((address_space(3))) T* lds, double* __restrict__ ws) {
@@ -655,12 +658,10 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
     for (int nb = 0; nb < WN; ++nb) acc[mb][nb] = (d4_t){0.0, 0.0, 0.0, 0.0};
 
   // Operand registers, two slots: the next step's operands are read from LDS while the current
-  // step's MFMAs run (FP32: the next step pair's).  The first step of stage s + 1 is read right after
-  // the barrier that ends stage s.  In FP64 that barrier sits before the MFMAs of stage s's last step
-  // (whose operands are already in registers), so those MFMAs cover the LDS latency at the stage
-  // boundary; FP32 tiles keep it after the last step pair (measured: holding its FP32 sums and the
-  // next stage's operands across the barrier spills the 4 x 4 tile and slows it by 8%).
-  constexpr bool EARLY = F64;
+  // step's MFMAs run (FP32: the next step pair's).  The barrier that ends stage s sits before the
+  // MFMAs of its last step (step pair), whose operands are already in registers; the first operands
+  // of stage s + 1 are read right after it, into the slot the last step leaves free, so those MFMAs
+  // cover the LDS latency at the stage boundary.
   T uA[2][WM], vA[2][WM], yB[2][WN];  // FP64 whole-tile step order
   typedef float f2_t __attribute__((ext_vector_type(2)));
   typedef const __attribute__((address_space(3))) f2_t* L2p;
@@ -703,13 +704,6 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
     fetch(lds + ((s + 1) & 1) * BUF, 0, 0);
     __builtin_amdgcn_sched_barrier(0);
   };
-  // FP32, after the stage's last step: the same wait and barrier; the next stage reads its first
-  // operands itself
-  auto stage_end = [&]() {
-    __builtin_amdgcn_sched_barrier(0);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-  };
 
   if (nstage > 0) {
 #pragma unroll
@@ -717,61 +711,107 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
   }
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  if constexpr (EARLY) {
+  if constexpr (F64) {
     if (nstage > 0) fetch(lds, 0, 0);
+  } else if constexpr (ROWOUTER) {
+    if (nstage > 0) fetch1(lds, 0, 0);
+  } else {
+    if (nstage > 0) fetchp(lds, 0, 0);
   }
+  // FP32 row-block-outer order: the stage sums of the row block in progress.  They are carried
+  // from one row block to the next, and from one stage to the next, until the first step of the
+  // following row block folds them into that block's FP64 accumulators (zeros before the first stage).
+  f4_t s32[WN];
+#pragma unroll
+  for (int nb = 0; nb < WN; ++nb) s32[nb] = f4_t{};
+  // FP32 whole-tile order: the stage sums of every block, folded during the next stage's first
+  // step pair (zeros before the first stage)
+  f4_t a32[WM][WN];
+#pragma unroll
+  for (int mb = 0; mb < WM; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < WN; ++nb) a32[mb][nb] = f4_t{};
   // one stage: MFMAs on the current buffer, copies of the next stage into the other
   auto run_stage = [&](int s) {
     const bool more = s + 1 < nstage;
     const __attribute__((address_space(3))) T* cur = lds + (s & 1) * BUF;
     if constexpr (ROWOUTER) {
       // FP32: one row block at a time over the stage's steps, so only WN blocks of FP32 stage sums
-      // are live; they go into the FP64 accumulators after the row block's last step.  The Y
-      // operands are read from LDS once per row block.
-      constexpr int NIT = WM * NPAIR;
-      fetch1(cur, 0, 0);
-      f4_t s32[WN];
+      // are live.  The Y operands are read from LDS once per row block.  A row block's sums go into
+      // its FP64 accumulators during the first step of the next row block, block by block just
+      // before the MFMA that restarts that block's sums: the MFMAs that produced them completed a
+      // whole step earlier, so the fold waits on nothing and runs beside the matrix pipe.
+      constexpr int NIT = WM * NPAIR;  // even: the first operands of a stage are always in slot 0
 #pragma unroll
       for (int it = 0; it < NIT; ++it) {
-        const int m = it % NPAIR, sl = it & 1;
+        const int mb = it / NPAIR, m = it % NPAIR, sl = it & 1;
         if (it + 1 < NIT) fetch1(cur, it + 1, sl ^ 1);
         const float av0 = ru[sl].x * rv[sl].x, av1 = ru[sl].y * rv[sl].y;
         f2_t bv[WN];
 #pragma unroll
         for (int nb = 0; nb < WN; ++nb) bv[nb] = ry[sl][nb];
+        if (it + 1 == NIT && more) {
+          // before the stage's last MFMAs: wait for this wave's copies of stage s + 1, barrier, then
+          // read its first operands, which those MFMAs cover
+          __builtin_amdgcn_sched_barrier(0);
+          asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+          __syncthreads();
+          fetch1(lds + ((s + 1) & 1) * BUF, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (m == 0) {
+          const int pb = (mb + WM - 1) % WM;  // the previous row block (of the previous stage at mb = 0)
 #pragma unroll
-        for (int nb = 0; nb < WN; ++nb)
-          s32[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av0, bv[nb].x, m == 0 ? f4_t{} : s32[nb], 0, 0, 0);
+          for (int nb = 0; nb < WN; ++nb) {
+            d4_t a = acc[pb][nb];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] += (double)s32[nb][r];
+            asm volatile("" : "+v"(a));  // keeps the fold here rather than sunk to the end of the stage
+            acc[pb][nb] = a;
+            s32[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av0, bv[nb].x, f4_t{}, 0, 0, 0);
+          }
+        } else {
+#pragma unroll
+          for (int nb = 0; nb < WN; ++nb)
+            s32[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av0, bv[nb].x, s32[nb], 0, 0, 0);
+        }
 #pragma unroll
         for (int nb = 0; nb < WN; ++nb)
           s32[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av1, bv[nb].y, s32[nb], 0, 0, 0);
+        // issue order (left to itself the compiler's scheduler issues the next step pair's LDS reads
+        // right before their use and waits for them there): the pair products, then the first WN
+        // MFMAs with the next operands' reads two at a time between them (each block's fold before
+        // its MFMA when a row block starts), then the second WN MFMAs
+        constexpr int NRD = 2 + WN;  // LDS reads of the next step pair
+        __builtin_amdgcn_sched_group_barrier(SG_VALU, 2, 0);
+#pragma unroll
+        for (int nb = 0; nb < WN; ++nb) {
+          if (m == 0) __builtin_amdgcn_sched_group_barrier(SG_VALU, 8, 0);
+          __builtin_amdgcn_sched_group_barrier(SG_MFMA, 1, 0);
+          if (2 * nb + 1 < NRD)
+            __builtin_amdgcn_sched_group_barrier(SG_DSR, 2, 0);
+          else if (2 * nb < NRD)
+            __builtin_amdgcn_sched_group_barrier(SG_DSR, 1, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(SG_MFMA, WN, 0);
+        if constexpr (2 * WN < NRD) __builtin_amdgcn_sched_group_barrier(SG_DSR, NRD - 2 * WN, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        // the next stage's copies, over every iteration but the last (whose barrier they precede)
         if (more) {
 #pragma unroll
           for (int i = 0; i < NCUV + NCY; ++i)
-            if (i % NIT == it) copy(s + 1, i);
-        }
-        if (m == NPAIR - 1) {
-          const int mb = it / NPAIR;
-#pragma unroll
-          for (int nb = 0; nb < WN; ++nb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[mb][nb][r] += (double)s32[nb][r];
+            if (i % (NIT - 1) == it) copy(s + 1, i);
         }
       }
-      stage_end();
       return;
     }
     if constexpr (!F64) {
-      // FP32 whole tile, one step pair per iteration
-      fetchp(cur, 0, 0);
-      f4_t a32[WM][WN];
-#pragma unroll
-      for (int mb = 0; mb < WM; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < WN; ++nb) a32[mb][nb] = f4_t{};
+      // FP32 whole tile, one step pair per iteration.  The previous stage's sums go into the FP64
+      // accumulators during this stage's first step pair, each block's just before the MFMA that
+      // restarts it (as in the row-block-outer order).
 #pragma unroll
       for (int m = 0; m < NPAIR; ++m) {
-        const int sl = m & 1;
+        const int sl = m & 1;  // NPAIR is even: the first operands of a stage are in slot 0
         if (m + 1 < NPAIR) fetchp(cur, m + 1, sl ^ 1);
         float av[2][WM];
 #pragma unroll
@@ -779,27 +819,55 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
           av[0][mb] = uP[sl][mb].x * vP[sl][mb].x;
           av[1][mb] = uP[sl][mb].y * vP[sl][mb].y;
         }
+        if (m + 1 == NPAIR && more) {
+          __builtin_amdgcn_sched_barrier(0);
+          asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+          __syncthreads();
+          fetchp(lds + ((s + 1) & 1) * BUF, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
+        }
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int mb = 0; mb < WM; ++mb)
 #pragma unroll
-          for (int mb = 0; mb < WM; ++mb)
+          for (int nb = 0; nb < WN; ++nb) {
+            if (m == 0) {
+              d4_t a = acc[mb][nb];
 #pragma unroll
-            for (int nb = 0; nb < WN; ++nb)
-              a32[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[h][mb], h ? yP[sl][nb].y : yP[sl][nb].x,
-                                                                 a32[mb][nb], 0, 0, 0);
+              for (int r = 0; r < 4; ++r) a[r] += (double)a32[mb][nb][r];
+              asm volatile("" : "+v"(a));  // keeps the fold here rather than sunk to the end of the stage
+              acc[mb][nb] = a;
+            }
+            a32[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0][mb], yP[sl][nb].x,
+                                                               m == 0 ? f4_t{} : a32[mb][nb], 0, 0, 0);
+          }
+#pragma unroll
+        for (int mb = 0; mb < WM; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < WN; ++nb)
+            a32[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1][mb], yP[sl][nb].y, a32[mb][nb], 0, 0, 0);
+        // issue order: the pair products, then the first WM x WN MFMAs with the next operands' reads
+        // two at a time between them (and each block's fold before its MFMA in the first step
+        // pair), then the second WM x WN MFMAs
+        constexpr int NRD = 2 * WM + WN;
+        __builtin_amdgcn_sched_group_barrier(SG_VALU, 2 * WM, 0);
+#pragma unroll
+        for (int b = 0; b < WM * WN; ++b) {
+          if (m == 0) __builtin_amdgcn_sched_group_barrier(SG_VALU, 8, 0);
+          __builtin_amdgcn_sched_group_barrier(SG_MFMA, 1, 0);
+          if (2 * b + 1 < NRD)
+            __builtin_amdgcn_sched_group_barrier(SG_DSR, 2, 0);
+          else if (2 * b < NRD)
+            __builtin_amdgcn_sched_group_barrier(SG_DSR, 1, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(SG_MFMA, WM * WN, 0);
+        if constexpr (2 * WM * WN < NRD) __builtin_amdgcn_sched_group_barrier(SG_DSR, NRD - 2 * WM * WN, 0);
+        __builtin_amdgcn_sched_barrier(0);
         if (more) {
 #pragma unroll
           for (int i = 0; i < NCUV + NCY; ++i)
-            if (i % NPAIR == m) copy(s + 1, i);
+            if (i % (NPAIR - 1) == m) copy(s + 1, i);
         }
       }
-#pragma unroll
-      for (int mb = 0; mb < WM; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < WN; ++nb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc[mb][nb][r] += (double)a32[mb][nb][r];
-      stage_end();
       return;
     }
     // FP64: one step per iteration
@@ -827,6 +895,21 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
     }
   };
   for (int s = 0; s < nstage; ++s) run_stage(s);
+  if constexpr (ROWOUTER) {
+    // the last row block's sums
+#pragma unroll
+    for (int nb = 0; nb < WN; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[WM - 1][nb][r] += (double)s32[nb][r];
+  } else if constexpr (!F64) {
+    // the last stage's sums
+#pragma unroll
+    for (int mb = 0; mb < WM; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < WN; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[mb][nb][r] += (double)a32[mb][nb][r];
+  }
   double* __restrict__ wt = ws + t.ws;
 #pragma unroll
   for (int mb = 0; mb < WM; ++mb)
