@@ -886,6 +886,22 @@ __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, co
 #pragma unroll
         for (int nb = 0; nb < WN; ++nb)
           acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+      // issue order: the pair products, then the MFMAs with the next step's LDS reads two at a time
+      // between the first ones
+      {
+        constexpr int NRD = 2 * WM + WN;
+        __builtin_amdgcn_sched_group_barrier(SG_VALU, WM, 0);
+#pragma unroll
+        for (int b = 0; b < WM * WN; ++b) {
+          __builtin_amdgcn_sched_group_barrier(SG_MFMA, 1, 0);
+          if (2 * b + 1 < NRD)
+            __builtin_amdgcn_sched_group_barrier(SG_DSR, 2, 0);
+          else if (2 * b < NRD)
+            __builtin_amdgcn_sched_group_barrier(SG_DSR, 1, 0);
+        }
+        if constexpr (2 * WM * WN < NRD) __builtin_amdgcn_sched_group_barrier(SG_DSR, NRD - 2 * WM * WN, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
       // the next stage's copies, spread over the steps (into the other buffer)
       if (more) {
 #pragma unroll
