@@ -536,6 +536,9 @@ struct ContractCfg {
   static constexpr int LDS_BYTES = 2 * BUF * (int)sizeof(T);
 };
 
+// Instruction classes of __builtin_amdgcn_sched_group_barrier (LLVM AMDGPU scheduling groups).
+constexpr int SG_VALU = 0x002, SG_MFMA = 0x008, SG_DSR = 0x100;
+
 // One work-group's tile: C[(u,v)][y] partial over chunks [kc0, kc0 + nkc) (nkc a multiple of SC).
 //
 // Staging uses direct global->LDS copies (global_load_lds_dwordx4): one wave instruction fills 64
@@ -543,9 +546,6 @@ struct ContractCfg {
 // rows [0, nu+nv) or the Y rows [MAXUV, MAXUV+np).  Each thread's source offset for every copy it
 // issues is computed once per tile; per stage only the chunk base moves.  The copies of stage s+1
 // are spread between the MFMA steps of stage s so their address work hides under the matrix pipe.
-// Instruction classes of __builtin_amdgcn_sched_group_barrier (LLVM AMDGPU scheduling groups).
-constexpr int SG_VALU = 0x002, SG_MFMA = 0x008, SG_DSR = 0x100;
-
 template <typename T, int WM, int WN, int SC_, int WR>
 __device__ __forceinline__ void contract_body(const TaskDev& __restrict__ Tk, const TileDev& t,
                                               __attribute__((address_space(3))) T* lds, double* __restrict__ ws) {
