@@ -274,6 +274,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
   store(0, 0);
   __syncthreads();
   const int nst = (nk + SY_K - 1) / SY_K;
+  // Operand registers, two slots: step s + 1's operands are read from LDS while step s's MFMAs run.
+  // The next stage's rows go into LDS and the barrier follows before the MFMAs of a stage's last step
+  // (whose operands are already in registers); the next stage's first operands are read right after
+  // the barrier, so those MFMAs cover that read.  SY_K / 4 is even: a stage starts in slot 0.
+  double av[2][4], bv[2][4];
+  auto operands = [&](const double* Ac, const double* Bc, int s, int slot) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) av[slot][m] = Ac[(4 * s + kl) * SY_LD + wm * 64 + m * 16 + lc];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) bv[slot][m] = Bc[(4 * s + kl) * SY_LD + wn * 64 + m * 16 + lc];
+  };
+  if (nst > 0) operands(As, Bs, 0, 0);
   for (int st = 0; st < nst; ++st) {
     const bool more = st + 1 < nst;
     if (more) load((st + 1) * SY_K);
@@ -281,18 +293,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
     const double* Bc = Bs + (st & 1) * BUF;
 #pragma unroll
     for (int s = 0; s < SY_K / 4; ++s) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) av[m] = Ac[(4 * s + kl) * SY_LD + wm * 64 + m * 16 + lc];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) bv[m] = Bc[(4 * s + kl) * SY_LD + wn * 64 + m * 16 + lc];
+      const int sl = s & 1;
+      if (s + 1 < SY_K / 4) {
+        operands(Ac, Bc, s + 1, sl ^ 1);
+      } else if (more) {
+        __builtin_amdgcn_sched_barrier(0);
+        store((st + 1) & 1, (st + 1) * SY_K);
+        __syncthreads();
+        operands(As + ((st + 1) & 1) * BUF, Bs + ((st + 1) & 1) * BUF, 0, sl ^ 1);
+        __builtin_amdgcn_sched_barrier(0);
+      }
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[sl][a], bv[sl][b], acc[a][b], 0, 0, 0);
+      // issue order: the next step's eight LDS reads two at a time between the first MFMAs
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);  // two LDS reads
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 12, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    if (more) store((st + 1) & 1, (st + 1) * SY_K);
-    __syncthreads();
   }
   // the tile: accumulator register r of lane (kl, lc) is row 4 r + kl, column lc of its 16 x 16 block
 #pragma unroll
