@@ -1005,21 +1005,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
 // A thread takes one pair row and 16 consecutive columns: per split it reads one whole 128-byte line
 // of the partial tile, so no line is fetched for a single value.  Consecutive threads take
 // consecutive pair rows: for (ab|P) those are consecutive b, so the output writes are contiguous.
+// Each item is shared by `spread` consecutive work-groups (interleaved 256-thread slices of its
+// rows), so that launches of few items still fill the device; every output element is still summed
+// by one thread in split order.
 __global__ __launch_bounds__(256) void reduce_kernel(const TaskDev* __restrict__ tasks,
                                                      const RedDev* __restrict__ reds,
                                                      const int32_t* __restrict__ items,
-                                                     const double* __restrict__ ws) {
-  const RedDev R = reds[items[blockIdx.x]];
+                                                     const double* __restrict__ ws, int spread) {
+  const int part = blockIdx.x % spread;
+  const RedDev R = reds[items[blockIdx.x / spread]];
   const TaskDev& T = tasks[R.task];
   const int64_t tile = (int64_t)R.bm * R.bn;
   const int ngrp = (R.np + 15) / 16;
-  for (int e = threadIdx.x; e < R.nrows * ngrp; e += 256) {
+  for (int e = part * 256 + threadIdx.x; e < R.nrows * ngrp; e += 256 * spread) {
     const int cg = e / R.nrows, row = e - cg * R.nrows;
     const int c0 = 16 * cg, nc = min(16, R.np - c0);
     double sum[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) sum[c] = 0.0;
     const double* p = ws + R.ws + (int64_t)row * R.bn + c0;
+#pragma unroll 2
     for (int k = 0; k < R.nsplit; ++k) {
       const double2* q = (const double2*)(p + k * tile);
 #pragma unroll
@@ -1430,7 +1435,10 @@ hipError_t launch_contract_mixed(int wm, int wn, int sc, int wr, const TaskDev* 
 hipError_t launch_reduce(const TaskDev* tasks, const RedDev* reds, const int32_t* items, int nitems,
                          const double* ws, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel, dim3(nitems), dim3(256), 0, st, tasks, reds, items, ws);
+  // up to four work-groups per item while the launch has fewer than 1024 items
+  const int spread = nitems >= 1024 ? 1 : std::min(4, (1023 + nitems) / nitems);
+  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)(nitems * spread)), dim3(256), 0, st, tasks, reds, items, ws,
+                     spread);
   return hipGetLastError();
 }
 
