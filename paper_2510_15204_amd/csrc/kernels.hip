@@ -1145,7 +1145,9 @@ __global__ __launch_bounds__(256) void chol_panel(const double* __restrict__ A, 
 }
 
 // Panel rows below the diagonal block: x D^T = a for each row.  Each wave solves two rows with one
-// entry per lane (lanes 0-31 one row, 32-63 the next); x_p is broadcast with a lane shuffle.
+// entry per lane (lanes 0-31 one row, 32-63 the next); x_p is broadcast with a lane shuffle.  A
+// work-group takes TRSM_ROWS rows, so each wave runs two of the row pairs' serial chains.
+constexpr int TRSM_ROWS = 16;
 __global__ __launch_bounds__(256) void chol_trsm(double* __restrict__ L, int n, int k0, const int* __restrict__ status) {
   __shared__ double D[CB][CB + 1];
   if (*status) return;
@@ -1157,8 +1159,8 @@ __global__ __launch_bounds__(256) void chol_trsm(double* __restrict__ L, int n, 
   }
   __syncthreads();
   const int lane = tid & 63, wave = tid >> 6, half = lane >> 5, q = lane & 31;
-  const int first = k0 + nb + blockIdx.x * 64;
-  for (int r = 0; r < 64; r += 8) {
+  const int first = k0 + nb + blockIdx.x * TRSM_ROWS;
+  for (int r = 0; r < TRSM_ROWS; r += 8) {
     const int i = first + r + wave * 2 + half;
     const bool live = i < n && q < nb;
     double x = live ? L[(int64_t)i * n + k0 + q] : 0.0;
@@ -1476,7 +1478,7 @@ hipError_t launch_cholesky(const double* A, double* L, int n, int* status, hipSt
     hipLaunchKernelGGL(chol_panel, dim3(1), dim3(256), 0, st, A, L, n, k0, status);
     const int m = n - k0 - CB;
     if (m > 0) {
-      hipLaunchKernelGGL(chol_trsm, dim3((m + 63) / 64), dim3(256), 0, st, L, n, k0, status);
+      hipLaunchKernelGGL(chol_trsm, dim3((m + TRSM_ROWS - 1) / TRSM_ROWS), dim3(256), 0, st, L, n, k0, status);
       const int t = (m + 63) / 64;
       hipLaunchKernelGGL(chol_update, dim3(t, t), dim3(256), 0, st, L, n, k0, status);
     }
